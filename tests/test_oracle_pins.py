@@ -1,0 +1,253 @@
+"""Pins of the FP64 oracle against what geometry fixes (no GPU).
+
+The paper prints no worked example or number for the method, so the oracle is
+pinned by: brute force on tiny inputs (every plane triple, no clipping); the
+stopping lemma (the certified cell equals the cell clipped by all N-1
+bisectors); an independent half-space intersection (scipy's Qhull) on medium
+inputs; closed forms (one point, a slab split, BCC and simple-cubic lattices,
+the 8 octant centres); invariants (volumes tile the box, symmetric neighbour
+relation, Euler's formula, equidistant vertices, empty spheres, equal face
+areas seen from both sides); and the Poisson-Voronoi mean face count.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+from paper_2412_04514_amd import gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(r):
+    return [list(x) for x in oracle.rows(r)]
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_oracle_matches_brute_force(seed):
+    """Neighbour sets equal, volumes to 1e-13 (abs, unit box), vertices to 1e-12."""
+    rng = np.random.default_rng(1000 + seed)
+    n = [2, 3, 5, 8, 13, 21, 34, 40][seed % 8]
+    if seed % 3 == 0:  # a tight clump plus a few far points
+        P = np.concatenate([0.5 + 0.02 * rng.standard_normal((n, 3)), rng.random((3, 3))])
+        P = np.clip(P, 0, 1)
+    else:
+        P = rng.random((n, 3))
+    lo, hi = ((0, 0, 0), (1, 1, 1)) if seed % 4 else ((-0.1, 0.0, -0.3), (1.2, 1.0, 1.05))
+    r = oracle.tessellate(P, lo, hi, vertices=True)
+    vol, nbrs, verts = brute.brute_cells(P, lo, hi)
+    np.testing.assert_allclose(r["volume"], vol, rtol=0, atol=1e-13)
+    assert _rows(r) == nbrs
+    for i in range(len(P)):
+        a, b = r["vrow_ptr"][i], r["vrow_ptr"][i + 1]
+        got = {tuple(int(x) for x in r["vplanes"][k]): r["vxyz"][k] for k in range(a, b)}
+        assert set(got) == set(verts[i])
+        for t, x in got.items():
+            np.testing.assert_allclose(x, verts[i][t], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind,n,seed", [("uniform", 1500, 0), ("cluster", 1500, 1), ("uniform", 400, 2)])
+def test_stopping_lemma(kind, n, seed):
+    """Certified early stop gives exactly the cell clipped by every bisector."""
+    # FP32-rounded inputs (as in the clustered workloads): q - p is then exact in
+    # FP64, so two clipping orders agree to rounding of the cell's own size.
+    if kind == "cluster":
+        P = gen.cluster(n, seed=seed, dtype=np.float32, n_clusters=8).astype(np.float64)
+    else:
+        P = getattr(gen, kind)(n, seed=seed, dtype=np.float64)
+    a = oracle.tessellate(P)
+    b = oracle.tessellate(P, all_planes=True)
+    assert np.array_equal(a["row_ptr"], b["row_ptr"]) and np.array_equal(a["col"], b["col"])
+    # 1e-12 relative, floored at 1e-14 of the mean cell volume: cells far below
+    # the mean size (cluster cores) carry rounding from the box-scale start.
+    np.testing.assert_allclose(a["volume"], b["volume"], rtol=1e-12, atol=1e-14 / n)
+
+
+def _inner(ns, cs, p):
+    """A strictly interior point: a quarter of the half nearest-neighbour distance
+    from the seed, toward the box centre (the seed itself may lie on a wall)."""
+    bis = np.abs(ns).sum(axis=1) > 0
+    dist = cs[6:] / np.linalg.norm(ns[6:], axis=1)
+    u = 0.5 - p
+    u = u / np.linalg.norm(u)
+    return 0.25 * dist.min() * u
+
+
+def test_against_halfspace_intersection():
+    """Volumes and neighbour sets against scipy's Qhull half-space intersection."""
+    from scipy.spatial import ConvexHull, HalfspaceIntersection
+    P = gen.cluster(300, seed=5, dtype=np.float64, n_clusters=6)
+    r = oracle.tessellate(P)
+    rows = _rows(r)
+    for i in range(len(P)):
+        ns, cs, ids = brute.halfspaces(P, i, (0, 0, 0), (1, 1, 1))
+        hs = np.hstack([ns, -cs[:, None]])
+        H = HalfspaceIntersection(hs, _inner(ns, cs, P[i]))
+        hull = ConvexHull(H.intersections)
+        assert abs(hull.volume - r["volume"][i]) <= 1e-10 * max(hull.volume, 1e-12)
+        act = np.abs(H.intersections @ ns.T - cs) <= 1e-9 * np.linalg.norm(ns, axis=1)
+        faces = sorted(int(ids[f]) for f in range(len(cs)) if ids[f] >= 0 and act[:, f].sum() >= 3)
+        # a plane touching >=3 vertices has positive area on generic input
+        assert faces == rows[i]
+
+
+def test_closed_forms():
+    with open(os.path.join(GOLDEN, "closed_forms.json")) as fh:
+        cases = json.load(fh)["cases"]
+    for case in cases:
+        P = np.array(case["points"], dtype=np.float64)
+        lo, hi = case.get("lo", [0, 0, 0]), case.get("hi", [1, 1, 1])
+        r = oracle.tessellate(P, lo, hi)
+        np.testing.assert_allclose(r["volume"], case["volume"], rtol=1e-13, atol=1e-15, err_msg=case["name"])
+        assert _rows(r) == case["neighbours"], case["name"]
+
+
+def _lattice_bcc(m):
+    """Simple-cubic part at (i+1/2)/m and body centres at (i+1)/m (binary exact for m=8)."""
+    g = (np.arange(m) + 0.5) / m
+    sc = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    h = np.arange(1, m) / m
+    bc = np.stack(np.meshgrid(h, h, h, indexing="ij"), -1).reshape(-1, 3)
+    return sc, bc
+
+
+def test_bcc_truncated_octahedra():
+    """Interior cells of a BCC lattice are truncated octahedra: volume a^3/2, 14 neighbours."""
+    m = 8
+    a = 1.0 / m
+    sc, bc = _lattice_bcc(m)
+    P = np.concatenate([sc, bc])
+    r = oracle.tessellate(P, vertices=True)
+    deg = np.diff(r["row_ptr"])
+    i_sc = np.all((sc > 1.4 * a) & (sc < 1 - 1.4 * a), axis=1)
+    i_bc = np.all((bc > 1.9 * a) & (bc < 1 - 1.9 * a), axis=1)
+    interior = np.concatenate([i_sc, i_bc])
+    assert interior.sum() > 100
+    np.testing.assert_allclose(r["volume"][interior], a ** 3 / 2, rtol=1e-12)
+    assert np.all(deg[interior] == 14)
+    # 24 vertices, each on exactly three faces
+    vr = np.diff(r["vrow_ptr"])
+    assert np.all(vr[interior] == 24)
+    assert abs(r["volume"].sum() - 1.0) < 1e-12
+
+
+def test_simple_cubic_lattice():
+    m = 8  # binary-exact lattice: degenerate planes pass exactly through vertices
+    g = (np.arange(m) + 0.5) / m
+    P = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    r = oracle.tessellate(P)
+    np.testing.assert_allclose(r["volume"], 1.0 / m ** 3, rtol=1e-12)
+    idx = np.rint(P * m - 0.5).astype(int)
+    expect = 6 - np.sum((idx == 0) | (idx == m - 1), axis=1)
+    assert np.array_equal(np.diff(r["row_ptr"]), expect)
+
+
+def _invariants(P, r, tol_rel=1e-12):
+    n = len(P)
+    rows = oracle.rows(r)
+    # volumes tile the box
+    assert abs(np.sum(np.sort(r["volume"])) - 1.0) < 1e-12
+    assert np.all(r["volume"] > 0)
+    # neighbour relation symmetric, face areas agree from both sides
+    area = {}
+    for i in range(n):
+        for k, j in enumerate(rows[i]):
+            area[(i, int(j))] = r["area"][r["row_ptr"][i] + k]
+    for (i, j), a in area.items():
+        assert (j, i) in area, (i, j)
+        # relative, floored at 1e-12 of the mean face scale (tiny cluster faces)
+        assert abs(area[(j, i)] - a) <= 1e-10 * a + 1e-12 * (1.0 / n) ** (2 / 3)
+    # closed convex polyhedra
+    assert np.all(r["euler"] == 2)
+    # generic vertices: three faces; equidistant from the generators of their faces
+    assert np.all(r["vdeg"] == 3)
+    from scipy.spatial import cKDTree
+    tree = cKDTree(P)
+    for i in range(n):
+        a, b = r["vrow_ptr"][i], r["vrow_ptr"][i + 1]
+        X = r["vxyz"][a:b]
+        d0 = np.linalg.norm(X - P[i], axis=1)
+        for k in range(a, b):
+            for j in r["vplanes"][k]:
+                if j >= 0:
+                    dj = np.linalg.norm(r["vxyz"][k] - P[j])
+                    assert abs(dj - d0[k - a]) <= tol_rel * d0[k - a] + 1e-15
+        # empty sphere: nothing strictly closer to a vertex than its own generator
+        dn, _ = tree.query(X, k=1)
+        assert np.all(dn >= d0 * (1 - 1e-12) - 1e-15)
+
+
+@pytest.mark.parametrize("kind,seed", [("uniform", 0), ("cluster", 1), ("filament", 2)])
+def test_invariants(kind, seed):
+    P = getattr(gen, kind)(3000, seed=seed, dtype=np.float64)
+    r = oracle.tessellate(P, vertices=True)
+    _invariants(P, r)
+
+
+def test_fp32_inputs_are_exact_in_fp64():
+    P = gen.uniform(2000, seed=7, dtype=np.float32)
+    r = oracle.tessellate(P.astype(np.float64), vertices=True)
+    _invariants(P.astype(np.float64), r)
+
+
+def test_poisson_voronoi_mean_faces():
+    """Typical Poisson-Voronoi cell: E[faces] = 2 + 48 pi^2 / 35 (Meijering 1953)."""
+    P = gen.uniform(200_000, seed=11, dtype=np.float64)
+    r = oracle.tessellate(P)
+    inner = np.all((P > 0.12) & (P < 0.88), axis=1)  # seeds chosen by position only
+    faces = np.diff(r["row_ptr"])[inner]
+    expect = 2 + 48 * np.pi ** 2 / 35
+    se = faces.std() / np.sqrt(len(faces))
+    assert abs(faces.mean() - expect) < 5 * se + 0.02, (faces.mean(), expect, se)
+    # and the mean cell volume is exactly the box volume over N
+    assert abs(r["volume"].mean() - 1 / len(P)) < 1e-18
+
+
+def test_validation_errors():
+    with pytest.raises(oracle.OracleError):
+        oracle.tessellate(np.array([[0.5, 0.5, 1.5]]))
+    with pytest.raises(oracle.OracleError):
+        oracle.tessellate(np.array([[0.5, 0.5, 0.5], [0.1, 0.2, 0.3], [0.5, 0.5, 0.5]]))
+    r = oracle.tessellate(np.zeros((0, 3)))
+    assert r["row_ptr"].tolist() == [0]
+
+
+def _kneeded_by_halfspaces(P, i, kmax):
+    """Least k with d_k^2 > 4 R_k^2, R_k from a Qhull intersection of the box and
+    the k nearest bisectors (exact (d^2, index) order)."""
+    from scipy.spatial import HalfspaceIntersection
+    d2 = np.sum((P - P[i]) ** 2, axis=1)
+    order = [j for j in np.lexsort((np.arange(len(P)), d2)) if j != i]
+    for k in range(1, min(kmax, len(P) - 1) + 1):
+        ns, cs, _ = brute.halfspaces(P, i, (0, 0, 0), (1, 1, 1), subset=order[:k])
+        H = HalfspaceIntersection(np.hstack([ns, -cs[:, None]]), _inner(ns, cs, P[i]))
+        R2 = np.max(np.sum(H.intersections ** 2, axis=1))
+        if d2[order[k - 1]] > 4 * R2:
+            return k
+    return len(P) - 1 if kmax >= len(P) - 1 else kmax + 1
+
+
+def test_kneeded_against_halfspaces():
+    P = gen.uniform(400, seed=3, dtype=np.float64)
+    cells = np.arange(0, 400, 20)
+    kn = oracle.kneeded(P, cells=cells, kcap=128)["kneeded"]
+    ref = [_kneeded_by_halfspaces(P, int(i), 128) for i in cells]
+    assert kn.tolist() == ref
+
+
+def test_kneeded_monotone_and_work():
+    P = gen.uniform(5000, seed=4, dtype=np.float64)
+    k = oracle.kneeded(P, kcap=4096, kwork=32)
+    kn = k["kneeded"]
+    assert kn.min() >= 1
+    # at list size 32, certified cells never test more planes than they have
+    cert = kn <= 32
+    assert np.all(k["tested"][cert] <= kn[cert])
+    assert np.all(k["tested"] <= 32)
+    # the exhaustive cell count: N=1 needs nothing, N=2 needs its one neighbour
+    assert oracle.kneeded(np.array([[0.3, 0.4, 0.5]]))["kneeded"].tolist() == [0]
+    two = oracle.kneeded(np.array([[0.3, 0.5, 0.5], [0.7, 0.5, 0.5]]))["kneeded"]
+    assert two.tolist() == [1, 1]
