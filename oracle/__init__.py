@@ -45,7 +45,7 @@ def _load():
         lib = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
-        lib.orc_tessellate.argtypes = [P, i64, P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)]
+        lib.orc_tessellate.argtypes = [P, i64, P, P, P, i64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)]
         lib.orc_tessellate.restype = ctypes.c_int
         lib.orc_nnz.argtypes = [P]
         lib.orc_nnz.restype = i64
@@ -74,8 +74,11 @@ class OracleError(ValueError):
 
 
 def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False, vertices=False,
-               threads=0) -> dict:
+               threads=0, cells=None) -> dict:
     """Exact cells of every point (rows in input order, neighbours ascending).
+
+    With ``cells`` (indices), only those rows are computed; the other rows are
+    empty with volume 0.
 
     ``all_planes`` clips by every other point (no early stop) -- the check of
     the stopping lemma.  Returns a dict with ``row_ptr, col, area, volume,
@@ -88,7 +91,9 @@ def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False,
     lo_, hi_ = _box(lo, hi)
     h = ctypes.c_void_p()
     flags = (1 if all_planes else 0) | (2 if vertices else 0)
-    rc = lib.orc_tessellate(_ptr(P), n, _ptr(lo_), _ptr(hi_), flags, threads, ctypes.byref(h))
+    c = None if cells is None else np.ascontiguousarray(cells, dtype=np.int64)
+    rc = lib.orc_tessellate(_ptr(P), n, _ptr(lo_), _ptr(hi_), _ptr(c), 0 if c is None else c.shape[0], flags,
+                            threads, ctypes.byref(h))
     if rc:
         raise OracleError(ERRORS.get(rc, str(rc)))
     try:

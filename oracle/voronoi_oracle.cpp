@@ -377,10 +377,11 @@ extern "C" {
 
 typedef struct Result orc_result;
 
-// Computes every cell.  flags: 1 = clip by all other points (no certificate),
-// 2 = keep vertices.  Returns 0, or 1 bad box, 2 point outside box, 3 duplicate.
-int orc_tessellate(const double* P, int64_t n, const double* lo, const double* hi, int flags, int nthreads,
-                   orc_result** out) {
+// Computes every cell, or only the cells listed in `cells` (others are left
+// empty).  flags: 1 = clip by all other points (no certificate), 2 = keep
+// vertices.  Returns 0, or 1 bad box, 2 point outside box, 3 duplicate.
+int orc_tessellate(const double* P, int64_t n, const double* lo, const double* hi, const int64_t* cells, int64_t nc,
+                   int flags, int nthreads, orc_result** out) {
   *out = nullptr;
   const int bad = validate(P, n, lo, hi);
   if (bad) return bad;
@@ -397,8 +398,11 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
   res->work.assign(4 * n, 0);
   res->euler.assign(n, 0);
   if (nthreads > 0) omp_set_num_threads(nthreads);
+  if (!cells) nc = n;
 #pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t t = 0; t < nc; ++t) {
+    const int64_t i = cells ? cells[t] : t;
+    if (i < 0 || i >= n) continue;
     Poly C;
     Work w;
     exact_cell(G, P, n, lo, hi, i, all, C, w);

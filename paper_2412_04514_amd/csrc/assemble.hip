@@ -1,0 +1,148 @@
+// Retry compaction (cells whose certificate failed) and output assembly: the
+// per-cell neighbour lists become one CSR "jagged array" of neighbour indices
+// (paper, Features section), rows in original input order by default or in
+// grid-sorted order, each row ascending; volumes and vertices follow.
+#include "internal.h"
+
+namespace votess {
+namespace {
+
+// Cells of `cells` (or 0..nc-1) whose status bit is in `mask`, appended to out
+// with one atomic per wave (order across waves is not fixed; every consumer
+// writes per-cell results by cell id).
+__global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ status, const int* __restrict__ cells,
+                                                 int nc, unsigned mask, int* __restrict__ out,
+                                                 int* __restrict__ count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int id = 0;
+  bool take = false;
+  if (t < nc) {
+    id = cells ? cells[t] : t;
+    take = (mask >> status[id]) & 1u;
+  }
+  const unsigned long long b = __ballot(take);
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0 && b) base = atomicAdd(count, __popcll(b));
+  base = __shfl(base, 0, 64);
+  if (take) out[base + __popcll(b & ((1ull << lane) - 1ull))] = id;
+}
+
+__global__ void k_rows_count(const int* __restrict__ nbr_count, const int* __restrict__ perm, int n, int sorted_space,
+                             int* __restrict__ counts) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  counts[sorted_space ? s : perm[s]] = nbr_count[s];
+}
+
+__global__ void k_rows_fill(const int* __restrict__ nbr_count, const int* __restrict__ nbr, int max_nbr,
+                            const int* __restrict__ perm, const double* __restrict__ vol_sorted, int n,
+                            int sorted_space, const long long* __restrict__ row_ptr, int* __restrict__ col,
+                            double* __restrict__ volume) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int r = sorted_space ? s : perm[s];
+  volume[r] = vol_sorted[s];
+  const int cnt = nbr_count[s];
+  int* dst = col + row_ptr[r];
+  const int* src = nbr + (size_t)s * max_nbr;
+  for (int e = 0; e < cnt; ++e) {  // insertion sort straight into the row
+    const int v = sorted_space ? src[e] : perm[src[e]];
+    int i = e;
+    while (i > 0 && dst[i - 1] > v) {
+      dst[i] = dst[i - 1];
+      --i;
+    }
+    dst[i] = v;
+  }
+}
+
+__global__ void k_vrows_count(const int* __restrict__ vcount, const int* __restrict__ perm, int n, int sorted_space,
+                              int* __restrict__ counts) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  counts[sorted_space ? s : perm[s]] = vcount[s];
+}
+
+__global__ void k_vrows_fill(const int* __restrict__ vcount, const double* __restrict__ verts,
+                             const int* __restrict__ vplanes, int max_vert, const int* __restrict__ perm, int n,
+                             int sorted_space, const long long* __restrict__ vrow_ptr, double* __restrict__ vxyz,
+                             int* __restrict__ vout) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int r = sorted_space ? s : perm[s];
+  const long long o = vrow_ptr[r];
+  const int cnt = vcount[s];
+  for (int e = 0; e < cnt; ++e) {
+    const size_t si = ((size_t)s * max_vert + e) * 3;
+    for (int a = 0; a < 3; ++a) {
+      vxyz[(o + e) * 3 + a] = verts[si + a];
+      const int p = vplanes[si + a];
+      vout[(o + e) * 3 + a] = (p < 0 || sorted_space) ? p : perm[p];
+    }
+  }
+}
+
+}  // namespace
+
+votess_status launch_compact_failed(const uint8_t* status, const int32_t* cells, int nc, int32_t* out_cells,
+                                    int32_t* d_count, uint8_t want_status_mask, hipStream_t st) {
+  VT_HIP(hipMemsetAsync(d_count, 0, sizeof(int), st));
+  if (nc == 0) return VOTESS_OK;
+  k_compact<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(status, cells, nc, want_status_mask, out_cells, d_count);
+  VT_HIP(hipGetLastError());
+  return VOTESS_OK;
+}
+
+votess_status launch_assemble(const int32_t* nbr_count, const int32_t* nbr, int max_nbr, const double* vol_sorted,
+                              const int32_t* perm, int n, int index_space, int64_t* row_ptr, int32_t* col,
+                              double* volume, Workspace& ws, hipStream_t st, int64_t* nnz_h) {
+  const unsigned b = (unsigned)((n + 255) / 256);
+  if (col == nullptr) {  // phase 1: counts -> row_ptr, nnz to the host
+    const size_t mark = ws.used;
+    int* counts = ws.take<int>(n > 0 ? n : 1);
+    if (n > 0) {
+      k_rows_count<<<b, 256, 0, st>>>(nbr_count, perm, n, index_space, counts);
+      VT_HIP(hipGetLastError());
+    }
+    VT_TRY(scan_i32_to_i64(counts, n, row_ptr, ws, st));
+    VT_HIP(hipMemcpyAsync(nnz_h, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    VT_HIP(hipStreamSynchronize(st));
+    ws.used = mark;
+    return VOTESS_OK;
+  }
+  if (n > 0) {  // phase 2: fill
+    k_rows_fill<<<b, 256, 0, st>>>(nbr_count, nbr, max_nbr, perm, vol_sorted, n, index_space,
+                                   (const long long*)row_ptr, col, volume);
+    VT_HIP(hipGetLastError());
+  }
+  return VOTESS_OK;
+}
+
+votess_status launch_assemble_vertices(const int32_t* vcount, const double* verts, const int32_t* vplanes,
+                                       int max_vert, const int32_t* perm, int n, int index_space,
+                                       int64_t* vrow_ptr, double* vxyz, int32_t* vout, Workspace& ws,
+                                       hipStream_t st, int64_t* nv_h) {
+  const unsigned b = (unsigned)((n + 255) / 256);
+  if (vxyz == nullptr) {
+    const size_t mark = ws.used;
+    int* counts = ws.take<int>(n > 0 ? n : 1);
+    if (n > 0) {
+      k_vrows_count<<<b, 256, 0, st>>>(vcount, perm, n, index_space, counts);
+      VT_HIP(hipGetLastError());
+    }
+    VT_TRY(scan_i32_to_i64(counts, n, vrow_ptr, ws, st));
+    VT_HIP(hipMemcpyAsync(nv_h, vrow_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    VT_HIP(hipStreamSynchronize(st));
+    ws.used = mark;
+    return VOTESS_OK;
+  }
+  if (n > 0) {
+    k_vrows_fill<<<b, 256, 0, st>>>(vcount, verts, vplanes, max_vert, perm, n, index_space,
+                                    (const long long*)vrow_ptr, vxyz, vout);
+    VT_HIP(hipGetLastError());
+  }
+  return VOTESS_OK;
+}
+
+}  // namespace votess

@@ -1,0 +1,706 @@
+// Cell clipping with the security-radius certificate (paper, Summary: each
+// cell is computed "by iteratively clipping a bounding box using the
+// perpendicular bisectors between the point and its nearby neighbors", and a
+// "security radius" condition proves it valid; the radius lemma is the one of
+// Ray et al. 2018, cited by the paper).
+//
+// MI355X design
+//  * A group of L lanes owns one cell; a 64-lane wave (= one workgroup) holds
+//    64/L cells.  Lane j of a group handles vertex slots t = j, j+L, ...
+//  * The polyhedron is kept in dual form in LDS: a list of clipping planes
+//    (box walls + bisectors, at most PMAX alive at once, slots recycled) and a
+//    list of triangles, one per vertex, each naming its three planes in
+//    counter-clockwise order seen from outside.  Vertex positions are cached
+//    next to the triangles, in seed-relative coordinates.
+//  * Clipping by plane m: every lane tests its vertices (n.v > c means
+//    outside), a ballot tells the group whether anything is cut.  For a cut,
+//    the directed dual edges of the removed triangles are marked in a per-cell
+//    bit matrix; an edge whose twin is unmarked lies on the boundary of the
+//    removed region and becomes a new triangle (a, b, m).  New vertices are
+//    solved from their three planes (Cramer), so no error accumulates from
+//    earlier vertices.  Then the alive-plane mask and the radius R^2 are
+//    rebuilt with group reductions.
+//  * Certificate: before plane m, the cell is final when d_m^2 > 4 R^2; after
+//    the list, when d_k^2 > 4 R^2 or the list holds every other point.
+//  * Volume: sum over vertices of corner terms det(F_f, v, e_fh - e_fg) / 6,
+//    with F_f the foot of the seed on face f and e_fg the point of line f^g
+//    nearest to the seed (a fan of each face from its foot, split at the edge
+//    anchors), accumulated in double.
+//  * F32_RECHECK: tests and radii in float; a plane-side test whose margin is
+//    below eps of its scale, and a certificate comparison with
+//    |d^2 - 4 R^2| <= eps d^2, are redone in double from the exact inputs.
+#include "internal.h"
+#include "device_common.h"
+
+#include <cfloat>
+
+namespace votess {
+namespace {
+
+constexpr unsigned kEmpty = 0xFFFFFFFFu;
+constexpr int ST_RUN = -1;
+
+struct ClipArgs {
+  const void* rec;
+  int n;
+  double lo0, lo1, lo2, hi0, hi1, hi2;
+  const int* cells;
+  int nc;
+  const int* knn;
+  int k;
+  double eps;
+  double dmargin;  // applied to d^2 in certificate tests (k-lists built in float)
+  int max_nbr, max_vert, out_by_id;
+  uint8_t* status;
+  int* nbr_count;
+  int* nbr;
+  double* volume;
+  int* kneeded;
+  int* vcount;
+  double* verts;
+  int* vplanes;
+  unsigned long long* counters;
+};
+
+template <typename R>
+struct V3 {
+  R x, y, z;
+};
+
+template <typename R>
+__device__ __forceinline__ V3<R> cross(const V3<R>& a, const V3<R>& b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ R dot(const V3<R>& a, const V3<R>& b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+
+// Vertex of planes a, b, c: solve [na; nb; nc] x = [ca, cb, cc].
+template <typename R>
+__device__ __forceinline__ V3<R> solve3(const V3<R>& na, R ca, const V3<R>& nb, R cb, const V3<R>& nc, R cc) {
+  const V3<R> bc = cross(nb, nc), ca_ = cross(nc, na), ab = cross(na, nb);
+  const R det = dot(na, bc);
+  const R inv = R(1) / det;
+  return {(ca * bc.x + cb * ca_.x + cc * ab.x) * inv, (ca * bc.y + cb * ca_.y + cc * ab.y) * inv,
+          (ca * bc.z + cb * ca_.z + cc * ab.z) * inv};
+}
+
+// Float vertex of three planes with a first-order forward error bound (max
+// norm): rounding of the cross products, the sums, the division and of the
+// plane data (normals may be off by an ulp, offsets by two).
+__device__ __forceinline__ V3<float> solve3_err(const V3<float>& na, float ca, const V3<float>& nb, float cb,
+                                                const V3<float>& nc, float cc, float& err) {
+  const V3<float> bc = cross(nb, nc), ca_ = cross(nc, na), ab = cross(na, nb);
+  auto perm = [](const V3<float>& a, const V3<float>& b) {
+    return V3<float>{fabsf(a.y * b.z) + fabsf(a.z * b.y), fabsf(a.z * b.x) + fabsf(a.x * b.z),
+                     fabsf(a.x * b.y) + fabsf(a.y * b.x)};
+  };
+  const V3<float> pbc = perm(nb, nc), pca = perm(nc, na), pab = perm(na, nb);
+  const float det = dot(na, bc);
+  const float inv = 1.0f / det;
+  const V3<float> v = {(ca * bc.x + cb * ca_.x + cc * ab.x) * inv, (ca * bc.y + cb * ca_.y + cc * ab.y) * inv,
+                       (ca * bc.z + cb * ca_.z + cc * ab.z) * inv};
+  const float u8 = 8.0f * (0.5f * FLT_EPSILON);
+  const float dD = u8 * (fabsf(na.x) * pbc.x + fabsf(na.y) * pbc.y + fabsf(na.z) * pbc.z);
+  const float aa = fabsf(ca), ab_ = fabsf(cb), ac = fabsf(cc);
+  const float ai = fabsf(inv);
+  const float ex = (u8 * (aa * pbc.x + ab_ * pca.x + ac * pab.x) + fabsf(v.x) * dD) * ai + FLT_EPSILON * fabsf(v.x);
+  const float ey = (u8 * (aa * pbc.y + ab_ * pca.y + ac * pab.y) + fabsf(v.y) * dD) * ai + FLT_EPSILON * fabsf(v.y);
+  const float ez = (u8 * (aa * pbc.z + ab_ * pca.z + ac * pab.z) + fabsf(v.z) * dD) * ai + FLT_EPSILON * fabsf(v.z);
+  err = fmaxf(ex, fmaxf(ey, ez));
+  return v;
+}
+
+template <typename M>
+__device__ __forceinline__ M bitm(int i) {
+  return M(1) << i;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor_w(T v, int m, int w) {
+  return __shfl_xor(v, m, w);
+}
+
+template <typename P, typename R, int L, int TMAX, int PMAX, bool RECHECK>
+__global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
+  using Rec4 = typename Rec<P>::type;
+  using M = typename std::conditional<(PMAX <= 32), unsigned, unsigned long long>::type;
+  constexpr int G = 64 / L;
+  constexpr int S = TMAX / L;
+  constexpr int TP = TMAX + 1;
+  constexpr unsigned long long LOWL = (L == 64) ? ~0ull : ((1ull << L) - 1);
+  constexpr M PFULL = (PMAX == 8 * (int)sizeof(M)) ? ~M(0) : ((M(1) << PMAX) - 1);
+  static_assert(S <= 32, "slot mask is 32 bits");
+
+  __shared__ R vx[G * TP], vy[G * TP], vz[G * TP];
+  __shared__ unsigned tri[G * TP];
+  __shared__ R pnx[G * PMAX], pny[G * PMAX], pnz[G * PMAX], pnc[G * PMAX];
+  __shared__ int pid[G * PMAX];
+  __shared__ M omask[G * PMAX];
+  __shared__ unsigned snew[G * PMAX];
+  constexpr int TE = RECHECK ? G * TP : 1;
+  __shared__ float verr[TE];  // forward error bound of each float vertex
+
+  const Rec4* rec = (const Rec4*)a.rec;
+  const int lane = threadIdx.x;
+  const int g = lane / L, j = lane % L;
+  const int gb = g * L;
+  const int vb = g * TP, pb = g * PMAX;
+  const long long t_idx = (long long)blockIdx.x * G + g;
+  const bool have = t_idx < a.nc;
+  const int sid = have ? (a.cells ? a.cells[t_idx] : (int)t_idx) : 0;
+  const int row = a.out_by_id ? sid : (int)t_idx;
+  const Rec4 pr = rec[sid];
+  const double p64x = pr.x, p64y = pr.y, p64z = pr.z;
+  const R px = (R)pr.x, py = (R)pr.y, pz = (R)pr.z;
+
+  auto group_any = [&](bool v) -> bool { return ((__ballot(v) >> gb) & LOWL) != 0ull; };
+  auto gor = [&](M v) -> M {
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) v |= shfl_xor_w(v, o, L);
+    return v;
+  };
+  auto gmax = [&](R v) -> R {
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) v = fmax(v, shfl_xor_w(v, o, L));
+    return v;
+  };
+  auto gmaxi = [&](int v) -> int {
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) v = max(v, shfl_xor_w(v, o, L));
+    return v;
+  };
+  auto gsumd = [&](double v) -> double {
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) v += shfl_xor_w(v, o, L);
+    return v;
+  };
+  auto gexcl = [&](int v, int& tot) -> int {
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) {
+      const int y = __shfl_up(x, o, L);
+      if (j >= o) x += y;
+    }
+    tot = __shfl(x, L - 1, L);
+    return x - v;
+  };
+
+  // FP64 plane of slot f, from the exact inputs (used by the recheck).
+  auto plane64 = [&](int f, V3<double>& n, double& c) {
+    const int id = pid[pb + f];
+    if (id >= 0) {
+      const Rec4 q = rec[id];
+      n = {(double)q.x - p64x, (double)q.y - p64y, (double)q.z - p64z};
+      c = 0.5 * dot(n, n);
+    } else {
+      const int w = -id - 1, ax = w >> 1;
+      const bool hi = w & 1;
+      const double lo_a = ax == 0 ? a.lo0 : (ax == 1 ? a.lo1 : a.lo2);
+      const double hi_a = ax == 0 ? a.hi0 : (ax == 1 ? a.hi1 : a.hi2);
+      const double p_a = ax == 0 ? p64x : (ax == 1 ? p64y : p64z);
+      const double sgn = hi ? 1.0 : -1.0;
+      n = {ax == 0 ? sgn : 0.0, ax == 1 ? sgn : 0.0, ax == 2 ? sgn : 0.0};
+      c = hi ? hi_a - p_a : p_a - lo_a;
+    }
+  };
+  auto vertex64 = [&](unsigned u) -> V3<double> {
+    V3<double> na, nb, nc;
+    double ca, cb, cc;
+    plane64(u & 0xFF, na, ca);
+    plane64((u >> 8) & 0xFF, nb, cb);
+    plane64((u >> 16) & 0xFF, nc, cc);
+    return solve3<double>(na, ca, nb, cb, nc, cc);
+  };
+
+  // ---- initial cell: the box, in seed-relative coordinates
+  for (int t = j; t < TMAX; t += L) tri[vb + t] = kEmpty;
+  for (int f = j; f < PMAX; f += L) omask[pb + f] = 0;
+  const R lx = (R)(a.lo0 - p64x), hx = (R)(a.hi0 - p64x);
+  const R ly = (R)(a.lo1 - p64y), hy = (R)(a.hi1 - p64y);
+  const R lz = (R)(a.lo2 - p64z), hz = (R)(a.hi2 - p64z);
+  for (int v = j; v < 8; v += L) {
+    const int bx = v & 1, by = (v >> 1) & 1, bz = (v >> 2) & 1;
+    vx[vb + v] = bx ? hx : lx;
+    vy[vb + v] = by ? hy : ly;
+    vz[vb + v] = bz ? hz : lz;
+    const unsigned X = bx, Y = 2 + by, Z = 4 + bz;
+    // (X, Y, Z) is counter-clockwise seen from outside iff an odd number of
+    // the three coordinates are on the high side
+    tri[vb + v] = ((bx + by + bz) & 1) ? (X | (Y << 8) | (Z << 16)) : (X | (Z << 8) | (Y << 16));
+    if (RECHECK) verr[vb + v] = FLT_EPSILON * fmax(fabs((double)vx[vb + v]), fmax(fabs((double)vy[vb + v]), fabs((double)vz[vb + v])));
+  }
+  for (int f = j; f < 6; f += L) {
+    const int ax = f >> 1;
+    const bool hi = f & 1;
+    const R sgn = hi ? R(1) : R(-1);
+    pnx[pb + f] = ax == 0 ? sgn : R(0);
+    pny[pb + f] = ax == 1 ? sgn : R(0);
+    pnz[pb + f] = ax == 2 ? sgn : R(0);
+    pnc[pb + f] = ax == 0 ? (hi ? hx : -lx) : (ax == 1 ? (hi ? hy : -ly) : (hi ? hz : -lz));
+    pid[pb + f] = -(f + 1);
+  }
+  int st = have ? ST_RUN : VOTESS_CELL_CERTIFIED;
+  int H = 8;
+  M alive = M(0x3F);
+  R R2 = fmax(lx * lx, hx * hx) + fmax(ly * ly, hy * hy) + fmax(lz * lz, hz * hz);
+  // largest vertex error bound (float path): widens the radius recheck window
+  float Emax = FLT_EPSILON * (float)sqrt((double)R2);
+  bool fmarg = false;  // the last F test was inside its recheck window
+  bool fprev = false;
+  int kneed = 0;
+  int nrecheck = 0;
+  __syncthreads();
+
+  // Recheck of the security radius in double: R^2 from vertices solved in FP64.
+  auto radius64 = [&](bool need) -> double {
+    double r2 = 0.0;
+    if (need) {
+      for (int t = j; t < H; t += L) {
+        const unsigned u = tri[vb + t];
+        if (u == kEmpty) continue;
+        const V3<double> v = vertex64(u);
+        r2 = fmax(r2, dot(v, v));
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) r2 = fmax(r2, shfl_xor_w(r2, o, L));
+    return r2;
+  };
+  const double kDmargin = a.dmargin;
+
+  int m = 0;
+  for (; m < a.k; ++m) {
+    bool run = st == ST_RUN;
+    if (!__any(run)) break;
+    int nb = -1;
+    R nx = 0, ny = 0, nz = 0, d2 = 0, c = 0;
+    if (run) {
+      nb = a.knn[(size_t)t_idx * a.k + m];
+      if (nb < 0) {  // padded list: it holds every other point
+        st = VOTESS_CELL_CERTIFIED;
+        kneed = m;
+        run = false;
+      }
+    }
+    bool cert_check = false, cert_recheck = false;
+    if (run) {
+      const Rec4 q = rec[nb];
+      nx = (R)q.x - px;
+      ny = (R)q.y - py;
+      nz = (R)q.z - pz;
+      d2 = nx * nx + ny * ny + nz * nz;
+      c = R(0.5) * d2;
+      cert_check = (R)(d2 * (R)kDmargin) > R(4) * R2;
+      if (RECHECK)
+        cert_recheck = fabs((double)d2 - 4.0 * (double)R2) <=
+                       a.eps * (double)d2 + 8.0 * sqrt((double)R2) * (double)Emax;
+    }
+    if (RECHECK) {
+      if (__any(cert_recheck)) {
+        const double r64 = radius64(cert_recheck);
+        if (cert_recheck) {
+          const Rec4 q = rec[nb];
+          const V3<double> n64 = {(double)q.x - p64x, (double)q.y - p64y, (double)q.z - p64z};
+          const double d64 = dot(n64, n64);
+          cert_check = d64 * kDmargin > 4.0 * r64;
+          if (fabs(d64 - 4.0 * r64) <= 1e-12 * d64) st = VOTESS_CELL_UNRESOLVED;
+          ++nrecheck;
+        }
+      }
+      if (st != ST_RUN) run = false;
+    }
+    if (run && cert_check) {
+      st = VOTESS_CELL_CERTIFIED;
+      kneed = fprev ? m : m + 1;
+      run = false;
+    }
+
+    // ---- test the plane against every vertex
+    unsigned out = 0;
+    bool unresolved = false;
+    if (run) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int t = j + L * s;
+        if (t < H) {
+          const unsigned u = tri[vb + t];
+          if (u != kEmpty) {
+            const R X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+            const R sv = nx * X + ny * Y + nz * Z - c;
+            bool o = sv > R(0);
+            if (RECHECK) {
+              const R scale = fabs(nx * X) + fabs(ny * Y) + fabs(nz * Z) + c;
+              const R nrm1 = fabs(nx) + fabs(ny) + fabs(nz);
+              if (fabs(sv) <= (R)a.eps * scale + nrm1 * (R)verr[vb + t]) {
+                const Rec4 q = rec[nb];
+                const V3<double> n64 = {(double)q.x - p64x, (double)q.y - p64y, (double)q.z - p64z};
+                const double c64 = 0.5 * dot(n64, n64);
+                const V3<double> v64 = vertex64(u);
+                const double s64 = dot(n64, v64) - c64;
+                const double sc64 = fabs(n64.x * v64.x) + fabs(n64.y * v64.y) + fabs(n64.z * v64.z) + c64;
+                if (fabs(s64) <= 1e-12 * sc64) unresolved = true;
+                o = s64 > 0.0;
+                ++nrecheck;
+              }
+            }
+            if (o) out |= 1u << s;
+          }
+        }
+      }
+    }
+    if (RECHECK) {
+      if (group_any(unresolved) && run) {
+        st = VOTESS_CELL_UNRESOLVED;
+        run = false;
+        out = 0;
+      }
+    }
+    const bool any_out = group_any(out != 0u);  // ballot by every lane
+    const bool cut = run && any_out;
+    if (!__any(cut)) {
+      if (run) {  // no cut: R unchanged and d_m^2 <= 4 R^2 (E_m was false)
+        fprev = false;
+        fmarg = false;
+      }
+      continue;
+    }
+
+    // ---- cut: new plane slot
+    int ps = -1;
+    bool doit = cut;
+    if (doit) {
+      const M fr = ~alive & PFULL;
+      if (fr == M(0)) {
+        st = VOTESS_CELL_CAPACITY;
+        doit = false;
+      } else {
+        ps = (sizeof(M) == 4) ? (__ffs((unsigned)fr) - 1) : (__ffsll((unsigned long long)fr) - 1);
+      }
+    }
+    if (doit && j == 0) {
+      pnx[pb + ps] = nx;
+      pny[pb + ps] = ny;
+      pnz[pb + ps] = nz;
+      pnc[pb + ps] = c;
+      pid[pb + ps] = nb;
+    }
+    if (!doit) out = 0;
+    // mark the directed dual edges of removed triangles
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if ((out >> s) & 1u) {
+        const unsigned u = tri[vb + j + L * s];
+        const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
+        atomicOr(&omask[pb + A], bitm<M>(B));
+        atomicOr(&omask[pb + B], bitm<M>(C));
+        atomicOr(&omask[pb + C], bitm<M>(A));
+      }
+    }
+    __syncthreads();
+    // boundary edges: twin not removed
+    int nbnd = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if ((out >> s) & 1u) {
+        const unsigned u = tri[vb + j + L * s];
+        const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
+        nbnd += !((omask[pb + B] >> A) & 1) + !((omask[pb + C] >> B) & 1) + !((omask[pb + A] >> C) & 1);
+      }
+    }
+    int btot;
+    int off = gexcl(nbnd, btot);
+    if (doit && (btot < 3 || btot > PMAX)) {  // inconsistent topology (rounding): give up on the cell
+      st = VOTESS_CELL_UNRESOLVED;
+      doit = false;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (doit && ((out >> s) & 1u)) {
+        const unsigned u = tri[vb + j + L * s];
+        const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
+        if (!((omask[pb + B] >> A) & 1)) snew[pb + off++] = A | (B << 8);
+        if (!((omask[pb + C] >> B) & 1)) snew[pb + off++] = B | (C << 8);
+        if (!((omask[pb + A] >> C) & 1)) snew[pb + off++] = C | (A << 8);
+      }
+    }
+    __syncthreads();
+    // clear the bit matrix rows and free the removed slots
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if ((out >> s) & 1u) {
+        const int t = j + L * s;
+        const unsigned u = tri[vb + t];
+        omask[pb + (u & 0xFF)] = 0;
+        omask[pb + ((u >> 8) & 0xFF)] = 0;
+        omask[pb + ((u >> 16) & 0xFF)] = 0;
+        if (doit) tri[vb + t] = kEmpty;
+      }
+    }
+    __syncthreads();
+    // new triangles (a, b, ps) into free slots, in slot order
+    int base = 0, hnew = 0;
+    const R mx = nx, my = ny, mz = nz, mc = c;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int t = j + L * s;
+      const bool fr = doit && tri[vb + t] == kEmpty;
+      const unsigned gbits = (unsigned)((__ballot(fr) >> gb) & LOWL);
+      const int r = base + __popc(gbits & ((1u << j) - 1u));
+      base += __popc(gbits);
+      if (fr && r < btot) {
+        const unsigned e = snew[pb + r];
+        const int A = e & 0xFF, B = (e >> 8) & 0xFF;
+        V3<R> v;
+        if constexpr (RECHECK) {
+          float e;
+          v = solve3_err({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
+                         pnc[pb + B], {mx, my, mz}, mc, e);
+          verr[vb + t] = e;
+        } else {
+          v = solve3<R>({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
+                        pnc[pb + B], {mx, my, mz}, mc);
+        }
+        vx[vb + t] = v.x;
+        vy[vb + t] = v.y;
+        vz[vb + t] = v.z;
+        tri[vb + t] = (unsigned)A | ((unsigned)B << 8) | ((unsigned)ps << 16);
+        hnew = t + 1;
+      }
+    }
+    if (doit && base < btot) {
+      st = VOTESS_CELL_CAPACITY;
+      doit = false;
+    }
+    hnew = gmaxi(hnew);
+    __syncthreads();
+    // rebuild the alive-plane mask and R^2
+    if (doit) H = max(H, hnew);
+    M al = 0;
+    R r2 = 0;
+    float em = 0.0f;
+    if (doit) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int t = j + L * s;
+        if (t < H) {
+          const unsigned u = tri[vb + t];
+          if (u != kEmpty) {
+            al |= bitm<M>(u & 0xFF) | bitm<M>((u >> 8) & 0xFF) | bitm<M>((u >> 16) & 0xFF);
+            const R X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+            r2 = fmax(r2, X * X + Y * Y + Z * Z);
+            if (RECHECK) em = fmaxf(em, verr[vb + t]);
+          }
+        }
+      }
+    }
+    al = gor(al);
+    r2 = gmax(r2);
+    if (RECHECK) {
+#pragma unroll
+      for (int o = 1; o < L; o <<= 1) em = fmaxf(em, shfl_xor_w(em, o, L));
+    }
+    if (doit) {
+      alive = al;
+      R2 = r2;
+      if (RECHECK) Emax = em;
+      fprev = (R)(d2 * (R)kDmargin) > R(4) * R2;
+      if (RECHECK)
+        fmarg = fabs((double)d2 - 4.0 * (double)R2) <= a.eps * (double)d2 + 8.0 * sqrt((double)R2) * (double)Emax;
+    }
+  }
+  // ---- end of the list: certified if d_k^2 > 4 R_k^2 or the list holds all others
+  if (RECHECK) {  // a marginal final radius test is redone in double
+    const bool need = st == ST_RUN && fmarg;
+    if (__any(need)) {
+      const double r64 = radius64(need);
+      if (need) {
+        const Rec4 q = rec[a.knn[(size_t)t_idx * a.k + a.k - 1]];
+        const V3<double> n64 = {(double)q.x - p64x, (double)q.y - p64y, (double)q.z - p64z};
+        const double d64 = dot(n64, n64);
+        fprev = d64 * kDmargin > 4.0 * r64;
+        if (fabs(d64 - 4.0 * r64) <= 1e-12 * d64) st = VOTESS_CELL_UNRESOLVED;
+        ++nrecheck;
+      }
+    }
+  }
+  if (st == ST_RUN) {
+    if (fprev || a.k >= a.n - 1) {
+      st = VOTESS_CELL_CERTIFIED;
+      kneed = a.k;
+    } else {
+      st = VOTESS_CELL_RADIUS;
+    }
+  }
+
+  // ---- outputs
+  const bool cert = have && st == VOTESS_CELL_CERTIFIED;
+  // volume: corner terms in double.  `exact` takes vertices and planes in
+  // double from the inputs (float path, ill-conditioned cells only).
+  auto anchor = [&](const V3<double>& nf, double cf, const V3<double>& ng, double cg) -> V3<double> {
+    const double g11 = dot(nf, nf), g12 = dot(nf, ng), g22 = dot(ng, ng);
+    const double det = g11 * g22 - g12 * g12;
+    const double al_ = (cf * g22 - cg * g12) / det, be = (cg * g11 - cf * g12) / det;
+    return {al_ * nf.x + be * ng.x, al_ * nf.y + be * ng.y, al_ * nf.z + be * ng.z};
+  };
+  auto cell_volume = [&](bool on, bool exact) -> double {
+    double acc = 0.0;
+    if (on) {
+      for (int t = j; t < H; t += L) {
+        const unsigned u = tri[vb + t];
+        if (u == kEmpty) continue;
+        V3<double> na, nb_, nc, v;
+        double ca, cb, cc;
+        if (exact) {
+          plane64(u & 0xFF, na, ca);
+          plane64((u >> 8) & 0xFF, nb_, cb);
+          plane64((u >> 16) & 0xFF, nc, cc);
+          v = solve3<double>(na, ca, nb_, cb, nc, cc);
+        } else {
+          const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
+          na = {(double)pnx[pb + A], (double)pny[pb + A], (double)pnz[pb + A]};
+          ca = (double)pnc[pb + A];
+          nb_ = {(double)pnx[pb + B], (double)pny[pb + B], (double)pnz[pb + B]};
+          cb = (double)pnc[pb + B];
+          nc = {(double)pnx[pb + C], (double)pny[pb + C], (double)pnz[pb + C]};
+          cc = (double)pnc[pb + C];
+          v = {(double)vx[vb + t], (double)vy[vb + t], (double)vz[vb + t]};
+        }
+        const V3<double> eab = anchor(na, ca, nb_, cb), ebc = anchor(nb_, cb, nc, cc), eca = anchor(nc, cc, na, ca);
+        const double fa = ca / dot(na, na), fb = cb / dot(nb_, nb_), fc = cc / dot(nc, nc);
+        const V3<double> Fa = {fa * na.x, fa * na.y, fa * na.z};
+        const V3<double> Fb = {fb * nb_.x, fb * nb_.y, fb * nb_.z};
+        const V3<double> Fc = {fc * nc.x, fc * nc.y, fc * nc.z};
+        acc += dot(Fa, cross(v, V3<double>{eca.x - eab.x, eca.y - eab.y, eca.z - eab.z}));
+        acc += dot(Fb, cross(v, V3<double>{eab.x - ebc.x, eab.y - ebc.y, eab.z - ebc.z}));
+        acc += dot(Fc, cross(v, V3<double>{ebc.x - eca.x, ebc.y - eca.y, ebc.z - eca.z}));
+      }
+    }
+    return gsumd(acc) / 6.0;
+  };
+  double vol = cell_volume(cert, false);
+  // Float vertices carry an absolute error ~u R; a cell much thinner than its
+  // radius (R^3 > 16 V, i.e. u R^3 / V > 1e-6) cannot get its volume to 1e-5
+  // from them, so its outputs are recomputed from vertices solved in double.
+  bool refine = false;
+  if (RECHECK) {
+    refine = cert && (double)R2 * sqrt((double)R2) > 16.0 * vol;
+    if (__any(refine)) {
+      const double v2 = cell_volume(refine, true);
+      if (refine) vol = v2;
+    }
+  }
+  // neighbours: alive bisector planes
+  int nnb = 0;
+  for (int f = j; f < PMAX; f += L) nnb += cert && ((alive >> f) & 1) && pid[pb + f] >= 0;
+  int ntot;
+  int noff = gexcl(nnb, ntot);
+  if (cert) {
+    for (int f = j; f < PMAX; f += L) {
+      if (((alive >> f) & 1) && pid[pb + f] >= 0) {
+        if (noff < a.max_nbr) a.nbr[(size_t)row * a.max_nbr + noff] = pid[pb + f];
+        ++noff;
+      }
+    }
+  }
+  // vertices
+  int vtot = 0;
+  if (a.max_vert > 0) {
+    int nv = 0;
+    for (int t = j; t < H; t += L) nv += cert && tri[vb + t] != kEmpty;
+    int voff = gexcl(nv, vtot);
+    if (cert) {
+      for (int t = j; t < H; t += L) {
+        const unsigned u = tri[vb + t];
+        if (u == kEmpty) continue;
+        if (voff < a.max_vert) {
+          const size_t o = ((size_t)row * a.max_vert + voff) * 3;
+          V3<double> v = {(double)vx[vb + t], (double)vy[vb + t], (double)vz[vb + t]};
+          if (refine) v = vertex64(u);
+          a.verts[o + 0] = p64x + v.x;
+          a.verts[o + 1] = p64y + v.y;
+          a.verts[o + 2] = p64z + v.z;
+          a.vplanes[o + 0] = pid[pb + (u & 0xFF)];
+          a.vplanes[o + 1] = pid[pb + ((u >> 8) & 0xFF)];
+          a.vplanes[o + 2] = pid[pb + ((u >> 16) & 0xFF)];
+        }
+        ++voff;
+      }
+    }
+  }
+  if (RECHECK) {
+    int rc = nrecheck;
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) rc += shfl_xor_w(rc, o, L);
+    nrecheck = rc;
+  }
+  if (have && j == 0) {
+    int fin = st;
+    if (fin == VOTESS_CELL_CERTIFIED && (ntot > a.max_nbr || (a.max_vert > 0 && vtot > a.max_vert)))
+      fin = VOTESS_CELL_CAPACITY;
+    a.status[row] = (uint8_t)fin;
+    a.nbr_count[row] = fin == VOTESS_CELL_CERTIFIED ? ntot : 0;
+    a.volume[row] = fin == VOTESS_CELL_CERTIFIED ? vol : 0.0;
+    if (a.kneeded) a.kneeded[row] = kneed;
+    if (a.vcount) a.vcount[row] = fin == VOTESS_CELL_CERTIFIED ? vtot : 0;
+    if (a.counters) {
+      if (nrecheck) atomicAdd(&a.counters[0], (unsigned long long)nrecheck);
+      if (fin == VOTESS_CELL_UNRESOLVED) atomicAdd(&a.counters[1], 1ull);
+      if (fin == VOTESS_CELL_CAPACITY) atomicAdd(&a.counters[2], 1ull);
+      if (refine && fin == VOTESS_CELL_CERTIFIED) atomicAdd(&a.counters[3], 1ull);
+    }
+  }
+}
+
+template <typename P, typename R, int L, int TMAX, int PMAX, bool RECHECK>
+votess_status run(const ClipArgs& ca, hipStream_t st) {
+  constexpr int G = 64 / L;
+  const unsigned blocks = (unsigned)((ca.nc + G - 1) / G);
+  k_clip<P, R, L, TMAX, PMAX, RECHECK><<<blocks, 64, 0, st>>>(ca);
+  VT_HIP(hipGetLastError());
+  return VOTESS_OK;
+}
+
+}  // namespace
+
+votess_status launch_clip(const ClipLaunch& a, hipStream_t st) {
+  if (a.nc == 0) return VOTESS_OK;
+  ClipArgs c;
+  c.rec = a.sorted;
+  c.n = a.n;
+  c.lo0 = a.lo[0]; c.lo1 = a.lo[1]; c.lo2 = a.lo[2];
+  c.hi0 = a.hi[0]; c.hi1 = a.hi[1]; c.hi2 = a.hi[2];
+  c.cells = a.cells;
+  c.nc = a.nc;
+  c.knn = a.knn;
+  c.k = a.k;
+  c.eps = a.eps;
+  // k-lists ordered by float distances may misplace near-ties by a few ulp:
+  // certify only with that much slack
+  c.dmargin = a.knn_dist == VOTESS_F32 ? (1.0 - 8.0 * (double)FLT_EPSILON) : 1.0;
+  c.max_nbr = a.max_nbr;
+  c.max_vert = a.max_vert;
+  c.out_by_id = a.out_by_id;
+  c.status = a.status;
+  c.nbr_count = a.nbr_count;
+  c.nbr = a.nbr;
+  c.volume = a.volume;
+  c.kneeded = a.kneeded;
+  c.vcount = a.vcount;
+  c.verts = a.verts;
+  c.vplanes = a.vplanes;
+  c.counters = a.counters;
+  const bool f32 = a.precision == VOTESS_CLIP_F32_RECHECK;
+  if (f32 && a.dtype != VOTESS_F32) return fail(VOTESS_EINVAL, "clip: F32_RECHECK needs F32 positions");
+  if (a.capacity == 0) {
+    if (f32) return run<float, float, 8, 64, 32, true>(c, st);
+    if (a.dtype == VOTESS_F32) return run<float, double, 8, 64, 32, false>(c, st);
+    return run<double, double, 8, 64, 32, false>(c, st);
+  }
+  if (f32) return run<float, float, 16, 256, 64, true>(c, st);
+  if (a.dtype == VOTESS_F32) return run<float, double, 16, 256, 64, false>(c, st);
+  return run<double, double, 16, 256, 64, false>(c, st);
+}
+
+}  // namespace votess
