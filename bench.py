@@ -1,0 +1,196 @@
+"""Throughput of the cell-by-cell Voronoi path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cluster-16m-f32]
+
+A step is one whole tessellation of the workload (grid sort, k-NN, clipping
+with the GPU retry ladder and stream phase, host fallback if any, CSR
+assembly) with the points already resident in HBM.  Prints one JSON line:
+cells/s for the headline configuration (learned-k, FP32 clipping with FP64
+rechecks, when a trained k-model is available; otherwise fixed-k FP32), the
+speedup over fixed-k FP64 on the same input, a roofline entry for the
+dominant kernel, and the CPU oracle timed on a bounded sample of the same
+workload on this machine's host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per cell of the method on the workload (nearest-first
+# clipping until the security radius certifies), measured by the oracle on a
+# 20000-cell sample with `python -m oracle.work_figures <workload> 20000`.
+ALGO_FLOPS_PER_CELL = {"cluster-16m-f32": 32586.95}
+
+PEAK = {"hbm_gbs": 8000.0, "fp32_tflops": 157.3, "fp64_tflops": 78.6}
+SORT_BYTES_PER_POINT = {np.float32: 12 + 16 + 4, np.float64: 24 + 32 + 4}  # read pts, write record + perm
+
+
+def knn_bytes_per_query(k: int) -> int:
+    return 16 + 4 * k  # read the query's record, write k indices
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cluster-16m-f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-baseline-f64", action="store_true")
+    ap.add_argument("--mode", choices=["auto", "fixed", "learned"], default="auto")
+    ap.add_argument("--k0", type=int, default=32)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the tessellation has no multi-GPU path here.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2412_04514_amd as vt
+    from paper_2412_04514_amd import gen
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    P = gen.make(args.workload, seed=0)
+    n = P.shape[0]
+    log(f"[bench] {args.workload}: {n} points generated in {time.time() - t0:.1f}s")
+    pts = torch.from_numpy(P).to(dev)
+    torch.cuda.synchronize()
+
+    kmodel = None
+    if args.mode in ("auto", "learned"):
+        try:
+            from paper_2412_04514_amd import kmodel as km
+            kmodel = km.load_default(args.workload)
+        except Exception as e:  # no trained model shipped for this workload
+            if args.mode == "learned":
+                raise
+            log(f"[bench] no learned-k model ({e}); timing fixed-k FP32")
+    headline = dict(precision="f32", k0=args.k0, max_gpu_retries=1)
+    label = "fixed-k FP32"
+    if kmodel is not None:
+        headline = dict(precision="f32", kmodel=kmodel, tau=kmodel.tau)
+        label = "learned-k FP32"
+
+    def run(cfg, steps, warmup, tag):
+        for i in range(warmup):
+            vt.tessellate(pts, **cfg)
+            log(f"[bench] {tag} warmup {i + 1}/{warmup}")
+        torch.cuda.synchronize()
+        stats = []
+        t = time.perf_counter()
+        for i in range(steps):
+            r = vt.tessellate(pts, **cfg)
+            stats.append(r.stats)
+            del r
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / steps
+        log(f"[bench] {tag}: {ms:.2f} ms/step")
+        return ms, stats
+
+    ms, stats = run(headline, args.steps, args.warmup, label)
+    mean = lambda key: float(np.mean([s[key] for s in stats]))  # noqa: E731
+    st0 = stats[-1]
+    ms_sort, ms_knn, ms_clip = mean("ms_sort"), mean("ms_knn"), mean("ms_clip")
+    ms_feat, ms_mlp = mean("ms_features"), mean("ms_mlp")
+
+    base = None
+    if not args.no_baseline_f64:
+        ms64, stats64 = run(dict(precision="f64", k0=32, max_gpu_retries=1), max(1, args.steps // 2), 1,
+                            "fixed-k FP64")
+        base = dict(ms_per_step=ms64, cells_per_s=n / (ms64 / 1e3), knn_clip_ms=float(
+            np.mean([s["ms_knn"] + s["ms_clip"] for s in stats64])), last_stats=stats64[-1])
+
+    # roofline of the dominant kernel (largest share of the step)
+    work = {"sort": ms_sort, "knn": ms_knn + ms_feat, "clip": ms_clip}
+    dom = max(work, key=work.get)
+    if dom == "clip":
+        flops = ALGO_FLOPS_PER_CELL.get(args.workload)
+        ach = flops * n / (ms_clip / 1e3) / 1e12 if flops else None
+        roof = dict(bound="alu", achieved=ach, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
+                    frac=(ach / PEAK["fp32_tflops"]) if ach else None, traffic=None,
+                    kernel="k_clip (all launches of a step)",
+                    per_unit=f"{flops} algorithmic flops per cell (oracle work count)")
+    elif dom == "knn":
+        nq = sum(p["cells"] for p in st0["passes"])
+        byt = sum(p["cells"] * knn_bytes_per_query(p["k"]) for p in st0["passes"])
+        ach = byt / (ms_knn / 1e3) / 1e9
+        roof = dict(bound="hbm", achieved=ach, peak=PEAK["hbm_gbs"], unit="GB/s", frac=ach / PEAK["hbm_gbs"],
+                    traffic=None, kernel="k_knn (all launches of a step)", per_unit="16 + 4k bytes per query",
+                    queries=nq)
+    else:
+        byt = SORT_BYTES_PER_POINT[P.dtype.type] * n
+        ach = byt / (ms_sort / 1e3) / 1e9
+        roof = dict(bound="hbm", achieved=ach, peak=PEAK["hbm_gbs"], unit="GB/s", frac=ach / PEAK["hbm_gbs"],
+                    traffic=None, kernel="grid sort", per_unit="32 bytes per point (f32)")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P)
+
+    knn_clip_ms = ms_knn + ms_clip + ms_feat + ms_mlp
+    out = {
+        "metric": "Voronoi cells/sec at 16M pts (kNN+clip); learned-k FP32 vs fixed-k FP64 speedup",
+        "value": n / (ms / 1e3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "points": n, "method": label, "box": "unit cube",
+                   "parallelism": "single GPU"},
+        "cells_per_s_knn_clip": n / (knn_clip_ms / 1e3),
+        "speedup_vs_fixed_k_f64": (base["ms_per_step"] / ms) if base else None,
+        "fixed_k_f64": {"ms_per_step": base["ms_per_step"], "cells_per_s": base["cells_per_s"],
+                        "knn_clip_ms": base["knn_clip_ms"]} if base else None,
+        "stage_ms": {"sort": ms_sort, "knn": ms_knn, "features": ms_feat, "mlp": ms_mlp, "clip": ms_clip,
+                     "assemble": mean("ms_assemble"), "fallback": mean("ms_fallback")},
+        "sort_gbs": SORT_BYTES_PER_POINT[P.dtype.type] * n / (ms_sort / 1e3) / 1e9,
+        "passes": st0["passes"],
+        "streamed_cells": st0["streamed_cells"], "fallback_cells": st0["fallback_cells"],
+        "capacity_cells": st0["capacity_cells"], "rechecks": st0["rechecks"],
+        "refined_cells": st0["refined_cells"], "unresolved_cells": st0["unresolved_cells"],
+        "bucket_cells": st0["bucket_cells"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline(P: np.ndarray) -> dict:
+    """The FP64 oracle on the points of the workload inside [0, 0.5)^3 (a
+    bounded sample, tessellated within that sub-box) on the host cores."""
+    import oracle
+    lo, hi = (0.0, 0.0, 0.0), (0.5, 0.5, 0.5)
+    sel = np.all(P < 0.5, axis=1)
+    S = P[sel].astype(np.float64)
+    threads = os.cpu_count() or 1
+    t = time.perf_counter()
+    oracle.tessellate(S, lo, hi, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": len(S) / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(S)} points of the workload inside [0,0.5)^3, tessellated in that sub-box "
+                      f"(FP64 C++ OpenMP oracle, {dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

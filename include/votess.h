@@ -157,6 +157,10 @@ typedef struct {
   int32_t max_vert;           /* row stride of verts / vplanes (0: no vertices) */
   int32_t capacity;           /* 0: fast kernel, 1: large-capacity kernel */
   int32_t out_by_id;          /* 1: write row cells[t] instead of row t */
+  int32_t stream;             /* 1: a cell its list does not certify keeps clipping by grid
+                                 rings (unbounded k); needs k-lists in the clip precision */
+  const votess_grid* grid;    /* stream only: the grid of votess_grid_sort */
+  const int32_t* cell_start;  /* stream only: [ncells+1] from votess_grid_sort */
 } votess_clip_opts;
 
 /* Clips the box by the bisectors of each cell's k-list, nearest first, and
@@ -198,6 +202,9 @@ typedef struct {
   int32_t host_fallback;    /* 1 (default): uncertified cells go to the CPU fallback */
   int32_t host_threads;     /* 0: all hardware threads */
   int32_t force_fail_every; /* >0: testing aid, every m-th cell skips the GPU passes */
+  int32_t gpu_stream;       /* 1 (default): the last GPU pass keeps clipping uncertified
+                               cells by grid rings (no bound on k) instead of leaving
+                               them to the host */
 } votess_params;
 
 #define VOTESS_MAX_PASSES 8
@@ -211,6 +218,7 @@ typedef struct {
   int64_t unresolved_cells; /* cells whose FP64 recheck stayed inside its bound */
   int64_t rechecks;         /* F32_RECHECK: predicates redone in FP64 (all passes) */
   int64_t refined_cells;    /* F32_RECHECK: thin cells whose outputs were solved in FP64 */
+  int64_t streamed_cells;   /* cells certified by the GPU stream phase */
   int64_t bucket_cells[8];  /* learned-k: cells per bucket */
   double ms_sort, ms_knn, ms_clip, ms_features, ms_mlp, ms_assemble, ms_fallback, ms_total;
 } votess_stats;

@@ -149,8 +149,12 @@ def knn(sorted_: torch.Tensor, grid: _lib.Grid, cell_start: torch.Tensor, k: int
 
 def clip_cells(sorted_: torch.Tensor, knn_: torch.Tensor, k: int, box=((0, 0, 0), (1, 1, 1)), cells=None,
                precision: str = "f64", eps: float = 1e-6, knn_dist: str | None = None, max_nbr: int = 64,
-               max_vert: int = 0, capacity: int = 0, kneeded: bool = True, ctx: Context | None = None) -> dict:
-    """Clips each cell by its k-list; per-cell status, neighbours, volume."""
+               max_vert: int = 0, capacity: int = 0, kneeded: bool = True, stream: bool = False, grid=None,
+               cell_start=None, ctx: Context | None = None) -> dict:
+    """Clips each cell by its k-list; per-cell status, neighbours, volume.
+
+    With ``stream`` (needs ``grid`` and ``cell_start``), a cell its list does
+    not certify keeps clipping by grid rings until certified."""
     ctx = ctx or Context.get()
     n = sorted_.shape[0]
     nc = n if cells is None else cells.shape[0]
@@ -174,6 +178,10 @@ def clip_cells(sorted_: torch.Tensor, knn_: torch.Tensor, k: int, box=((0, 0, 0)
     o.max_vert = max_vert
     o.capacity = capacity
     o.out_by_id = 0
+    o.stream = int(bool(stream))
+    if stream:
+        o.grid = C.cast(C.pointer(grid), C.c_void_p)
+        o.cell_start = cell_start.data_ptr()
     b = _box(box)
     check(ctx.lib.votess_clip_cells(ctx.handle, _ptr(sorted_), _dtype_code(sorted_), n, C.byref(b), _ptr(cells), nc,
                                     _ptr(knn_), int(k), C.byref(o), _ptr(out["status"]), _ptr(out["nbr_count"]),
@@ -202,7 +210,8 @@ class Result:
 def tessellate(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), k0: int = 32, max_gpu_retries: int = 1,
                precision: str = "f64", eps: float = 1e-6, pts_per_cell: float = 2.0, kmodel=None, tau: float = 0.9,
                vertices: bool = False, index_space: str = "original", host_fallback: bool = True,
-               host_threads: int = 0, force_fail_every: int = 0, ctx: Context | None = None) -> Result:
+               host_threads: int = 0, force_fail_every: int = 0, gpu_stream: bool = True,
+               ctx: Context | None = None) -> Result:
     """Voronoi cells of ``points`` [n,3] (cuda, float32/float64) clipped to ``box``."""
     ctx = ctx or Context.get(points.device.index)
     pts = points.contiguous()
@@ -220,6 +229,7 @@ def tessellate(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), k0: int = 32, m
     p.host_fallback = int(bool(host_fallback))
     p.host_threads = host_threads
     p.force_fail_every = force_fail_every
+    p.gpu_stream = int(bool(gpu_stream))
     r = _lib.Result()
     b = _box(box)
     n = pts.shape[0]

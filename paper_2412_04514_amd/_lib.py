@@ -29,21 +29,22 @@ class Grid(C.Structure):
 
 class ClipOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("eps", C.c_double), ("knn_dist", C.c_int), ("max_nbr", C.c_int32),
-                ("max_vert", C.c_int32), ("capacity", C.c_int32), ("out_by_id", C.c_int32)]
+                ("max_vert", C.c_int32), ("capacity", C.c_int32), ("out_by_id", C.c_int32),
+                ("stream", C.c_int32), ("grid", C.c_void_p), ("cell_start", C.c_void_p)]
 
 
 class Params(C.Structure):
     _fields_ = [("k0", C.c_int32), ("max_gpu_retries", C.c_int32), ("pts_per_cell", C.c_double),
                 ("precision", C.c_int), ("eps", C.c_double), ("kmodel", C.c_void_p), ("tau", C.c_double),
                 ("want_vertices", C.c_int32), ("index_space", C.c_int32), ("host_fallback", C.c_int32),
-                ("host_threads", C.c_int32), ("force_fail_every", C.c_int32)]
+                ("host_threads", C.c_int32), ("force_fail_every", C.c_int32), ("gpu_stream", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("npasses", C.c_int32), ("pass_k", C.c_int32 * MAX_PASSES), ("pass_cells", C.c_int64 * MAX_PASSES),
                 ("pass_failed", C.c_int64 * MAX_PASSES), ("capacity_cells", C.c_int64),
                 ("fallback_cells", C.c_int64), ("unresolved_cells", C.c_int64), ("rechecks", C.c_int64),
-                ("refined_cells", C.c_int64), ("bucket_cells", C.c_int64 * 8),
+                ("refined_cells", C.c_int64), ("streamed_cells", C.c_int64), ("bucket_cells", C.c_int64 * 8),
                 ("ms_sort", C.c_double), ("ms_knn", C.c_double), ("ms_clip", C.c_double),
                 ("ms_features", C.c_double), ("ms_mlp", C.c_double), ("ms_assemble", C.c_double),
                 ("ms_fallback", C.c_double), ("ms_total", C.c_double)]
@@ -54,7 +55,7 @@ class Stats(C.Structure):
                             for i in range(n)],
                     capacity_cells=self.capacity_cells, fallback_cells=self.fallback_cells,
                     unresolved_cells=self.unresolved_cells, rechecks=self.rechecks,
-                    refined_cells=self.refined_cells, bucket_cells=list(self.bucket_cells)[:NBUCKET],
+                    refined_cells=self.refined_cells, streamed_cells=self.streamed_cells, bucket_cells=list(self.bucket_cells)[:NBUCKET],
                     ms_sort=self.ms_sort, ms_knn=self.ms_knn, ms_clip=self.ms_clip, ms_features=self.ms_features,
                     ms_mlp=self.ms_mlp, ms_assemble=self.ms_assemble, ms_fallback=self.ms_fallback,
                     ms_total=self.ms_total)

@@ -293,6 +293,13 @@ votess_status votess_clip_cells(votess_ctx* ctx, const void* sorted, votess_dtyp
   a.verts = verts;
   a.vplanes = vplanes;
   a.counters = nullptr;
+  a.stream = opts->stream;
+  if (opts->stream) {
+    if (!opts->grid || !opts->cell_start) return fail(VOTESS_EINVAL, "clip: stream needs grid and cell_start");
+    VT_TRY(check_grid(opts->grid));
+    a.grid = to_dev(*opts->grid);
+    a.cell_start = opts->cell_start;
+  }
   return launch_clip(a, (hipStream_t)stream);
 }
 
@@ -311,6 +318,7 @@ void votess_params_default(votess_params* p) {
   p->host_fallback = 1;
   p->host_threads = 0;
   p->force_fail_every = 0;
+  p->gpu_stream = 1;
 }
 
 void votess_result_free(votess_ctx* ctx, votess_result* r) {
@@ -436,6 +444,12 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   base.vplanes = wantv ? vplanes.get<int32_t>() : nullptr;
   base.counters = counters.get<unsigned long long>();
   const GridDev GD = to_dev(grid);
+  base.grid = GD;
+  base.cell_start = cell_start.get<int32_t>();
+  // the last list pass on the GPU streams uncertified cells on by grid rings
+  const bool stream_last = P.gpu_stream != 0 && P.force_fail_every == 0;
+  int nretry = 0;
+  for (int kk = P.k0; nretry < P.max_gpu_retries && kk < 64; ++nretry) kk = std::min(2 * kk, 64);
 
   // ---- first pass over all cells
   int k = P.k0;
@@ -461,6 +475,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
         c.nc = n;
         c.knn = knn.get<int32_t>();
         c.k = k;
+        c.stream = stream_last && nretry == 0;
         VT_TRY(launch_clip(c, st));
       }
       S.pass_k[S.npasses] = k;
@@ -503,9 +518,10 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     c2.knn = knn2.get<int32_t>();
     c2.k = kk;
     c2.capacity = 1;
+    c2.stream = stream_last;
     return launch_clip(c2, st);
   };
-  for (int r = 0; r < P.max_gpu_retries && nfail > 0 && P.force_fail_every == 0 && k < 64; ++r) {
+  for (int r = 0; r < nretry && nfail > 0 && P.force_fail_every == 0 && k < 64; ++r) {
     k = std::min(2 * k, 64);
     VT_TRY(alloc_buf(ctx, knn, (size_t)nfail * k * 4));
     {
@@ -520,6 +536,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
       c.nc = nfail;
       c.knn = knn.get<int32_t>();
       c.k = k;
+      c.stream = stream_last && r == nretry - 1;
       VT_TRY(launch_clip(c, st));
     }
     VT_TRY(capacity_pass(cur, nfail, k));
@@ -542,12 +559,13 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
                                      (1u << VOTESS_CELL_UNRESOLVED),
                                  st));
     VT_HIP(hipMemcpyAsync(&nhost, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
-    unsigned long long cnt[4] = {0, 0, 0, 0};
+    unsigned long long cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     VT_HIP(hipMemcpyAsync(cnt, counters.p, sizeof(cnt), hipMemcpyDeviceToHost, st));
     VT_HIP(hipStreamSynchronize(st));
     S.unresolved_cells = (int64_t)cnt[1];
     S.rechecks = (int64_t)cnt[0];
     S.refined_cells = (int64_t)cnt[3];
+    S.streamed_cells = (int64_t)cnt[4];
   }
   if (nhost > 0) {
     if (!P.host_fallback)

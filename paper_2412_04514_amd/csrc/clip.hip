@@ -60,6 +60,10 @@ struct ClipArgs {
   double* verts;
   int* vplanes;
   unsigned long long* counters;
+  // stream phase (cells the list did not certify keep clipping by grid rings)
+  int stream;
+  const int* cell_start;
+  GridDev grid;
 };
 
 template <typename R>
@@ -122,7 +126,7 @@ __device__ __forceinline__ T shfl_xor_w(T v, int m, int w) {
   return __shfl_xor(v, m, w);
 }
 
-template <typename P, typename R, int L, int TMAX, int PMAX, bool RECHECK>
+template <typename P, typename R, int L, int TMAX, int PMAX, bool RECHECK, bool STREAM>
 __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
   using Rec4 = typename Rec<P>::type;
   using M = typename std::conditional<(PMAX <= 32), unsigned, unsigned long long>::type;
@@ -245,8 +249,21 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
   int H = 8;
   M alive = M(0x3F);
   R R2 = fmax(lx * lx, hx * hx) + fmax(ly * ly, hy * hy) + fmax(lz * lz, hz * hz);
-  // largest vertex error bound (float path): widens the radius recheck window
-  float Emax = FLT_EPSILON * (float)sqrt((double)R2);
+  // float path: bounds on the true R^2 from each vertex's forward error bound,
+  // R2lo <= R^2 <= R2hi; a radius test is rechecked only between them
+  float R2hi, R2lo;
+  {
+    const double r = sqrt((double)R2), e = FLT_EPSILON * r;
+    R2hi = (float)((r + e) * (r + e) * (1.0 + 1e-6));
+    R2lo = (float)((r - e) * (r - e) * (1.0 - 1e-6));
+  }
+  // radius predicates of the float path: certain / uncertain (else certainly not)
+  auto rad_certain = [&](R dd2) -> bool {
+    return (double)dd2 * a.dmargin * (1.0 - a.eps) > 4.0 * (double)R2hi;
+  };
+  auto rad_uncertain = [&](R dd2) -> bool {
+    return !rad_certain(dd2) && (double)dd2 * a.dmargin * (1.0 + a.eps) > 4.0 * (double)R2lo;
+  };
   bool fmarg = false;  // the last F test was inside its recheck window
   bool fprev = false;
   int kneed = 0;
@@ -270,53 +287,9 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
   };
   const double kDmargin = a.dmargin;
 
-  int m = 0;
-  for (; m < a.k; ++m) {
-    bool run = st == ST_RUN;
-    if (!__any(run)) break;
-    int nb = -1;
-    R nx = 0, ny = 0, nz = 0, d2 = 0, c = 0;
-    if (run) {
-      nb = a.knn[(size_t)t_idx * a.k + m];
-      if (nb < 0) {  // padded list: it holds every other point
-        st = VOTESS_CELL_CERTIFIED;
-        kneed = m;
-        run = false;
-      }
-    }
-    bool cert_check = false, cert_recheck = false;
-    if (run) {
-      const Rec4 q = rec[nb];
-      nx = (R)q.x - px;
-      ny = (R)q.y - py;
-      nz = (R)q.z - pz;
-      d2 = nx * nx + ny * ny + nz * nz;
-      c = R(0.5) * d2;
-      cert_check = (R)(d2 * (R)kDmargin) > R(4) * R2;
-      if (RECHECK)
-        cert_recheck = fabs((double)d2 - 4.0 * (double)R2) <=
-                       a.eps * (double)d2 + 8.0 * sqrt((double)R2) * (double)Emax;
-    }
-    if (RECHECK) {
-      if (__any(cert_recheck)) {
-        const double r64 = radius64(cert_recheck);
-        if (cert_recheck) {
-          const Rec4 q = rec[nb];
-          const V3<double> n64 = {(double)q.x - p64x, (double)q.y - p64y, (double)q.z - p64z};
-          const double d64 = dot(n64, n64);
-          cert_check = d64 * kDmargin > 4.0 * r64;
-          if (fabs(d64 - 4.0 * r64) <= 1e-12 * d64) st = VOTESS_CELL_UNRESOLVED;
-          ++nrecheck;
-        }
-      }
-      if (st != ST_RUN) run = false;
-    }
-    if (run && cert_check) {
-      st = VOTESS_CELL_CERTIFIED;
-      kneed = fprev ? m : m + 1;
-      run = false;
-    }
-
+  // Tests plane (n, c) of candidate nb against every vertex and, if it cuts,
+  // replaces the removed triangles.  Called by every lane (wave-uniform).
+  auto apply_plane = [&](bool run, R nx, R ny, R nz, R c, R d2, int nb) {
     // ---- test the plane against every vertex
     unsigned out = 0;
     bool unresolved = false;
@@ -364,7 +337,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
         fprev = false;
         fmarg = false;
       }
-      continue;
+      return;
     }
 
     // ---- cut: new plane slot
@@ -457,6 +430,15 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
           float e;
           v = solve3_err({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
                          pnc[pb + B], {mx, my, mz}, mc, e);
+          const float vm = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+          if (!(e <= 16.0 * a.eps * vm)) {
+            // ill-conditioned float vertex: solve it in double from the exact
+            // planes and keep the rounded value (bound: one ulp)
+            const V3<double> w = vertex64((unsigned)A | ((unsigned)B << 8) | ((unsigned)ps << 16));
+            v = {(float)w.x, (float)w.y, (float)w.z};
+            e = FLT_EPSILON * (float)fmax(fabs(w.x), fmax(fabs(w.y), fabs(w.z)));
+            ++nrecheck;
+          }
           verr[vb + t] = e;
         } else {
           v = solve3<R>({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
@@ -479,7 +461,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     if (doit) H = max(H, hnew);
     M al = 0;
     R r2 = 0;
-    float em = 0.0f;
+    float em = 0.0f, eml = 0.0f;
     if (doit) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -490,7 +472,12 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
             al |= bitm<M>(u & 0xFF) | bitm<M>((u >> 8) & 0xFF) | bitm<M>((u >> 16) & 0xFF);
             const R X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
             r2 = fmax(r2, X * X + Y * Y + Z * Z);
-            if (RECHECK) em = fmaxf(em, verr[vb + t]);
+            if (RECHECK) {
+              const float n2 = (float)(X * X + Y * Y + Z * Z), n1 = (float)(fabs(X) + fabs(Y) + fabs(Z));
+              const float e = verr[vb + t];
+              em = fmaxf(em, n2 + e * (2.0f * n1 + e));
+              eml = fmaxf(eml, n2 - 2.0f * e * n1);
+            }
           }
         }
       }
@@ -499,16 +486,75 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     r2 = gmax(r2);
     if (RECHECK) {
 #pragma unroll
-      for (int o = 1; o < L; o <<= 1) em = fmaxf(em, shfl_xor_w(em, o, L));
+      for (int o = 1; o < L; o <<= 1) {
+        em = fmaxf(em, shfl_xor_w(em, o, L));
+        eml = fmaxf(eml, shfl_xor_w(eml, o, L));
+      }
     }
     if (doit) {
       alive = al;
       R2 = r2;
-      if (RECHECK) Emax = em;
-      fprev = (R)(d2 * (R)kDmargin) > R(4) * R2;
-      if (RECHECK)
-        fmarg = fabs((double)d2 - 4.0 * (double)R2) <= a.eps * (double)d2 + 8.0 * sqrt((double)R2) * (double)Emax;
+      if (RECHECK) {
+        R2hi = em * (1.0f + 4.0f * FLT_EPSILON);
+        R2lo = eml * (1.0f - 4.0f * FLT_EPSILON);
+        fprev = rad_certain(d2);
+        fmarg = rad_uncertain(d2);
+      } else {
+        fprev = (R)(d2 * (R)kDmargin) > R(4) * R2;
+      }
     }
+  };
+
+  int m = 0;
+  for (; m < a.k; ++m) {
+    bool run = st == ST_RUN;
+    if (!__any(run)) break;
+    int nb = -1;
+    R nx = 0, ny = 0, nz = 0, d2 = 0, c = 0;
+    if (run) {
+      nb = a.knn[(size_t)t_idx * a.k + m];
+      if (nb < 0) {  // padded list: it holds every other point
+        st = VOTESS_CELL_CERTIFIED;
+        kneed = m;
+        run = false;
+      }
+    }
+    bool cert_check = false, cert_recheck = false;
+    if (run) {
+      const Rec4 q = rec[nb];
+      nx = (R)q.x - px;
+      ny = (R)q.y - py;
+      nz = (R)q.z - pz;
+      d2 = dist2_nc(nx, ny, nz);
+      c = R(0.5) * d2;
+      if (RECHECK) {
+        cert_check = rad_certain(d2);
+        cert_recheck = rad_uncertain(d2);
+      } else {
+        cert_check = (R)(d2 * (R)kDmargin) > R(4) * R2;
+      }
+    }
+    if (RECHECK) {
+      if (__any(cert_recheck)) {
+        const double r64 = radius64(cert_recheck);
+        if (cert_recheck) {
+          const Rec4 q = rec[nb];
+          const V3<double> n64 = {(double)q.x - p64x, (double)q.y - p64y, (double)q.z - p64z};
+          const double d64 = dot(n64, n64);
+          cert_check = d64 * kDmargin > 4.0 * r64;
+          if (fabs(d64 - 4.0 * r64) <= 1e-12 * d64) st = VOTESS_CELL_UNRESOLVED;
+          ++nrecheck;
+        }
+      }
+      if (st != ST_RUN) run = false;
+    }
+    if (run && cert_check) {
+      st = VOTESS_CELL_CERTIFIED;
+      kneed = fprev ? m : m + 1;
+      run = false;
+    }
+
+    apply_plane(run, nx, ny, nz, c, d2, nb);
   }
   // ---- end of the list: certified if d_k^2 > 4 R_k^2 or the list holds all others
   if (RECHECK) {  // a marginal final radius test is redone in double
@@ -532,6 +578,163 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     } else {
       st = VOTESS_CELL_RADIUS;
     }
+  }
+
+
+  // ---- stream phase: a cell its list did not certify keeps clipping by grid
+  // rings around its seed, restricted to the bounding box of its "flower" (the
+  // union of the balls centred at its vertices that pass through the seed: a
+  // point outside every such ball is on the inner side of its bisector at
+  // every vertex, so it cannot cut; flowers only shrink as the cell does).
+  // Points already in the list are skipped by their (d^2, sorted index) key,
+  // points beyond the security radius by d^2 > 4 R^2.  The cell is final once
+  // the scanned block of rings contains the flower box.
+  if constexpr (STREAM) {
+    const int ik0 = (have && st == VOTESS_CELL_RADIUS) ? a.knn[(size_t)t_idx * a.k + a.k - 1] : -1;
+    const bool strm = ik0 >= 0;  // a full list that did not certify
+    if (strm) st = ST_RUN;
+    const GridDev& Gd = a.grid;
+    const int cx = axis_cell(p64x, Gd.lo0, Gd.ih0, Gd.g0);
+    const int cy = axis_cell(p64y, Gd.lo1, Gd.ih1, Gd.g1);
+    const int cz = axis_cell(p64z, Gd.lo2, Gd.ih2, Gd.g2);
+    const double gmarg = 1e-9 * fmax(Gd.hi0 - Gd.lo0, fmax(Gd.hi1 - Gd.lo1, Gd.hi2 - Gd.lo2));
+    R dk2 = R(0);
+    int ik = -1;
+    if (strm) {
+      ik = ik0;
+      const Rec4 q = rec[ik];
+      dk2 = dist2_nc((R)q.x - px, (R)q.y - py, (R)q.z - pz);
+    }
+    // flower box in grid cells, from the current vertices (group reduction)
+    int fb0 = 0, fb1 = -1, fb2 = 0, fb3 = -1, fb4 = 0, fb5 = -1;
+    auto flower_box = [&]() {
+      double mn0 = 1e300, mn1 = 1e300, mn2 = 1e300, mx0 = -1e300, mx1 = -1e300, mx2 = -1e300;
+      for (int t = j; t < H; t += L) {
+        if (tri[vb + t] == kEmpty) continue;
+        const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+        const double rad = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-6) + (RECHECK ? 2.0 * (double)verr[vb + t] : 0.0);
+        mn0 = fmin(mn0, X - rad); mx0 = fmax(mx0, X + rad);
+        mn1 = fmin(mn1, Y - rad); mx1 = fmax(mx1, Y + rad);
+        mn2 = fmin(mn2, Z - rad); mx2 = fmax(mx2, Z + rad);
+      }
+#pragma unroll
+      for (int o = 1; o < L; o <<= 1) {
+        mn0 = fmin(mn0, shfl_xor_w(mn0, o, L)); mx0 = fmax(mx0, shfl_xor_w(mx0, o, L));
+        mn1 = fmin(mn1, shfl_xor_w(mn1, o, L)); mx1 = fmax(mx1, shfl_xor_w(mx1, o, L));
+        mn2 = fmin(mn2, shfl_xor_w(mn2, o, L)); mx2 = fmax(mx2, shfl_xor_w(mx2, o, L));
+      }
+      fb0 = axis_cell(p64x + mn0 - gmarg, Gd.lo0, Gd.ih0, Gd.g0);
+      fb1 = axis_cell(p64x + mx0 + gmarg, Gd.lo0, Gd.ih0, Gd.g0);
+      fb2 = axis_cell(p64y + mn1 - gmarg, Gd.lo1, Gd.ih1, Gd.g1);
+      fb3 = axis_cell(p64y + mx1 + gmarg, Gd.lo1, Gd.ih1, Gd.g1);
+      fb4 = axis_cell(p64z + mn2 - gmarg, Gd.lo2, Gd.ih2, Gd.g2);
+      fb5 = axis_cell(p64z + mx2 + gmarg, Gd.lo2, Gd.ih2, Gd.g2);
+    };
+    int rr = -1, zz = 0, yy = 0, part = 0, zhi = -1, ylo = 0, yhi = -1;
+    int jcur = 0, jend = 0;
+    unsigned pend = 0;
+    int myj = -1;
+    R myd2 = R(0);
+    const R skip_scale = RECHECK ? R(1) - R(2e-6) : R(1) - R(1e-12);
+    while (__any(strm && st == ST_RUN)) {
+      const bool act = strm && st == ST_RUN;
+      // refill this group's batch of candidates (group-uniform loop)
+      if (act && pend == 0u) {
+        bool done = false;
+        while (!done) {
+          if (jcur >= jend) {
+            // next run of the ring: one contiguous x-range of grid cells
+            bool have_run = false;
+            while (!have_run) {
+              if (rr < 0 || zz > zhi) {
+                // ring rr finished (or none yet): final when the block contains the flower box
+                flower_box();
+                if (rr >= 0 && cx - rr <= fb0 && cx + rr >= fb1 && cy - rr <= fb2 && cy + rr >= fb3 &&
+                    cz - rr <= fb4 && cz + rr >= fb5) {
+                  done = true;
+                  break;
+                }
+                ++rr;
+                zz = max(cz - rr, fb4);
+                zhi = min(cz + rr, fb5);
+                ylo = max(cy - rr, fb2);
+                yhi = min(cy + rr, fb3);
+                yy = ylo;
+                part = 0;
+                if (ylo > yhi) zz = zhi + 1;  // empty ring
+                continue;
+              }
+              const bool face = zz == cz - rr || zz == cz + rr || yy == cy - rr || yy == cy + rr;
+              int x0 = 1, x1 = 0;
+              if (part == 0) {
+                if (face) { x0 = max(cx - rr, fb0); x1 = min(cx + rr, fb1); }
+                else if (cx - rr >= fb0) { x0 = x1 = cx - rr; }
+                part = 1;
+              } else if (part == 1) {
+                if (!face && rr > 0 && cx + rr <= fb1) { x0 = x1 = cx + rr; }
+                part = 2;
+              } else {
+                part = 0;
+                if (++yy > yhi) { yy = ylo; ++zz; }
+                continue;
+              }
+              if (x0 <= x1) {
+                const int row = Gd.g0 * (yy + Gd.g1 * zz);
+                jcur = a.cell_start[row + x0];
+                jend = a.cell_start[row + x1 + 1];
+                have_run = jcur < jend;
+              }
+            }
+            if (done) break;
+          }
+          // batch of L candidates, one per lane, filtered by list key and radius
+          const int jj = jcur + j;
+          bool pass = false;
+          myj = -1;
+          if (jj < jend && jj != sid) {
+            const Rec4 q = rec[jj];
+            const R d2c = dist2_nc((R)q.x - px, (R)q.y - py, (R)q.z - pz);
+            const bool beyond_list = d2c > dk2 || (d2c == dk2 && jj > ik);
+            pass = beyond_list && d2c * skip_scale <= R(4) * (RECHECK ? (R)R2hi : R2);
+            myj = jj;
+            myd2 = d2c;
+          }
+          jcur += L;
+          pend = (unsigned)((__ballot(pass) >> gb) & LOWL);
+          if (!pass) myj = -1;
+          if (pend) break;
+        }
+        if (done) {
+          st = VOTESS_CELL_CERTIFIED;
+          kneed = a.k + 1;
+        }
+      }
+      // nearest pending candidate of the group
+      bool run2 = act && st == ST_RUN && pend != 0u;
+      R best = (run2 && myj >= 0 && ((pend >> j) & 1u)) ? myd2 : R(3.0e38);
+      int bl = j;
+#pragma unroll
+      for (int o = 1; o < L; o <<= 1) {
+        const R ob = shfl_xor_w(best, o, L);
+        const int ol = shfl_xor_w(bl, o, L);
+        if (ob < best || (ob == best && ol < bl)) { best = ob; bl = ol; }
+      }
+      const int nb2 = __shfl(myj, gb + bl, 64);
+      R nx = 0, ny = 0, nz = 0, c = 0, d2 = 0;
+      if (run2) {
+        pend &= ~(1u << bl);
+        const Rec4 q = rec[nb2];
+        nx = (R)q.x - px;
+        ny = (R)q.y - py;
+        nz = (R)q.z - pz;
+        d2 = dist2_nc(nx, ny, nz);
+        c = R(0.5) * d2;
+        // the radius may have shrunk since the batch was filtered
+        if (d2 * skip_scale > R(4) * (RECHECK ? (R)R2hi : R2)) run2 = false;
+      }
+      apply_plane(run2, nx, ny, nz, c, d2, nb2);
+    }
+    if (strm && st == VOTESS_CELL_CERTIFIED && j == 0 && a.counters) atomicAdd(&a.counters[4], 1ull);
   }
 
   // ---- outputs
@@ -657,7 +860,10 @@ template <typename P, typename R, int L, int TMAX, int PMAX, bool RECHECK>
 votess_status run(const ClipArgs& ca, hipStream_t st) {
   constexpr int G = 64 / L;
   const unsigned blocks = (unsigned)((ca.nc + G - 1) / G);
-  k_clip<P, R, L, TMAX, PMAX, RECHECK><<<blocks, 64, 0, st>>>(ca);
+  if (ca.stream)
+    k_clip<P, R, L, TMAX, PMAX, RECHECK, true><<<blocks, 64, 0, st>>>(ca);
+  else
+    k_clip<P, R, L, TMAX, PMAX, RECHECK, false><<<blocks, 64, 0, st>>>(ca);
   VT_HIP(hipGetLastError());
   return VOTESS_OK;
 }
@@ -691,8 +897,14 @@ votess_status launch_clip(const ClipLaunch& a, hipStream_t st) {
   c.verts = a.verts;
   c.vplanes = a.vplanes;
   c.counters = a.counters;
+  c.stream = a.stream;
+  c.cell_start = a.cell_start;
+  c.grid = a.grid;
   const bool f32 = a.precision == VOTESS_CLIP_F32_RECHECK;
   if (f32 && a.dtype != VOTESS_F32) return fail(VOTESS_EINVAL, "clip: F32_RECHECK needs F32 positions");
+  if (a.stream && (a.knn_dist == VOTESS_F32) != f32)
+    return fail(VOTESS_EINVAL, "clip: the stream phase needs k-lists built in the clip precision");
+  if (a.stream && !a.cell_start) return fail(VOTESS_EINVAL, "clip: the stream phase needs cell_start");
   if (a.capacity == 0) {
     if (f32) return run<float, float, 8, 64, 32, true>(c, st);
     if (a.dtype == VOTESS_F32) return run<float, double, 8, 64, 32, false>(c, st);

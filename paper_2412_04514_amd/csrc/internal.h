@@ -114,7 +114,10 @@ struct ClipLaunch {
   int32_t* vcount;
   double* verts;
   int32_t* vplanes;
-  unsigned long long* counters;  // [4]: rechecks, unresolved, capacity, (spare) -- nullable
+  unsigned long long* counters;  // [8]: rechecks, unresolved, capacity, refined, streamed -- nullable
+  int stream = 0;                // 1: uncertified cells continue by grid rings
+  const int32_t* cell_start = nullptr;
+  GridDev grid{};
 };
 votess_status launch_clip(const ClipLaunch& a, hipStream_t st);
 

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64) void k_knn(const typename Rec<T>::type* __restr
       if (j == s) continue;
       const auto qr = rec[j];
       const D dx = (D)qr.x - px, dy = (D)qr.y - py, dz = (D)qr.z - pz;
-      const D d2 = dx * dx + dy * dy + dz * dz;
+      const D d2 = dist2_nc(dx, dy, dz);
       if (L.better(d2, j)) L.insert(d2, j);
     }
   };

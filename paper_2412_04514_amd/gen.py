@@ -32,30 +32,57 @@ def _inside(p: np.ndarray) -> np.ndarray:
 
 def _dup_mask(p: np.ndarray) -> np.ndarray:
     """True for every row that repeats an earlier row (exact bit equality)."""
-    if p.shape[0] < 2:
-        return np.zeros(p.shape[0], dtype=bool)
-    ut = np.uint32 if p.dtype == np.float32 else np.uint64
-    b = np.ascontiguousarray(p).view(ut).reshape(-1, 3)
+    n = p.shape[0]
+    dup = np.zeros(n, dtype=bool)
+    if n < 2:
+        return dup
+    if p.dtype == np.float32:
+        b = np.ascontiguousarray(p).view(np.uint32).reshape(-1, 3)
+        key = (b[:, 0].astype(np.uint64) << np.uint64(32)) | b[:, 1].astype(np.uint64)
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        same = ks[1:] == ks[:-1]
+        if not same.any():
+            return dup
+        # rows sharing (x, y): settle on z among them only
+        idx = np.unique(np.concatenate([order[1:][same], order[:-1][same]]))
+        sub = _dup_mask_lex(b[idx])
+        dup[idx[sub]] = True
+        return dup
+    return _dup_mask_lex(np.ascontiguousarray(p).view(np.uint64).reshape(-1, 3))
+
+
+def _dup_mask_lex(b: np.ndarray) -> np.ndarray:
     order = np.lexsort((b[:, 2], b[:, 1], b[:, 0]))
     s = b[order]
     same = np.all(s[1:] == s[:-1], axis=1)
-    dup = np.zeros(p.shape[0], dtype=bool)
+    dup = np.zeros(b.shape[0], dtype=bool)
     dup[order[1:][same]] = True
     return dup
 
 
 def _finish(rng, draw, n: int, dtype) -> np.ndarray:
-    """Round to dtype, redraw rejects and duplicates, shuffle."""
+    """Round to dtype, redraw rejects (outside the cube) and duplicates, shuffle."""
     out = draw(n).astype(dtype)
-    for _ in range(1000):
-        bad = ~_inside(out)
-        bad |= _dup_mask(out)
-        nb = int(bad.sum())
-        if nb == 0:
+
+    def redraw_outside(rows):
+        for _ in range(1000):
+            bad = rows[~_inside(out[rows])]
+            if bad.size == 0:
+                return
+            out[bad] = draw(bad.size).astype(dtype)
+            rows = bad
+        raise RuntimeError("could not draw in-box points")  # pragma: no cover
+
+    redraw_outside(np.arange(n))
+    for _ in range(100):
+        dup = np.nonzero(_dup_mask(out))[0]
+        if dup.size == 0:
             break
-        out[bad] = draw(nb).astype(dtype)
+        out[dup] = draw(dup.size).astype(dtype)
+        redraw_outside(dup)
     else:  # pragma: no cover - would need an absurd generator
-        raise RuntimeError("could not draw a duplicate-free in-box set")
+        raise RuntimeError("could not draw a duplicate-free set")
     return out[rng.permutation(n)]
 
 
