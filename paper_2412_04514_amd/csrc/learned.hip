@@ -1,26 +1,765 @@
-// Learned-k form: placeholder until the network kernels land.
+// Learned list size: a small network proposes each cell's k from local
+// density features; the security-radius certificate still judges every cell,
+// so results do not depend on the network.
+//
+//  * k_features   12 features per query from its 16-NN list and the grid.
+//  * k_mlp        BF16 MFMA (v_mfma_f32_16x16x16bf16_1k, FP32 accumulate)
+//                 forward pass for 16-sample tiles; in training mode also
+//                 softmax cross-entropy and the backward pass, accumulating
+//                 per-block weight gradients with MFMA (sum over samples
+//                 as the K dimension).  Inference writes the chosen bucket.
+//  * k_reduce     deterministic fixed-order sum of the per-block partials.
+//  * k_adam       Adam on FP32 master weights.
+//
+// MFMA operand layout (16x16x16, wave64, lane l, element i = 0..3):
+//   A[m][k]: m = l % 16, k = 4 (l / 16) + i;   B[k][n]: k = 4 (l / 16) + i, n = l % 16
+//   D[m][n]: m = 4 (l / 16) + i, n = l % 16
+// so a product's D registers are, unchanged, the A operand of its transpose
+// and the B operand of a product over the same rows; the other hand-offs go
+// through LDS.
 #include "internal.h"
+#include "device_common.h"
+
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+
+namespace votess {
+constexpr int NF = VOTESS_NFEAT, NH = VOTESS_NHID, NO = VOTESS_NBUCKET;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NF, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
+              OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NO * NH, NPARAM = OFF_B3 + NO;
+static_assert(NPARAM == VOTESS_NPARAM, "parameter layout");
+constexpr int kSamplesPerBlock = 64;  // four 16-sample tiles per wave
+}  // namespace votess
 
 struct votess_kmodel {
-  votess_ctx* ctx;
+  votess_ctx* ctx = nullptr;
+  float* theta = nullptr;  // [NPARAM] FP32 master weights
+  float* m = nullptr;      // Adam moments
+  float* v = nullptr;
+  float* norm = nullptr;   // [24]: mean[12], std[12]
+  float* grads = nullptr;  // [NPARAM]
+  float* partial = nullptr;
+  int partial_blocks = 0;
+  int step = 0;
 };
 
 namespace votess {
-votess_status learned_first_pass(votess_ctx*, votess_kmodel*, double, const void*, int, const votess_grid&,
-                                 const int32_t*, const ClipLaunch&, int32_t*, int32_t*, votess_stats&, hipStream_t) {
-  return fail(VOTESS_EINVAL, "learned-k is not built yet");
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
 }
+__device__ __forceinline__ float bf16_round(float f) { return __uint_as_float((unsigned)bf16_bits(f) << 16); }
+__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
+  bf16x4 r;
+  r[0] = (short)bf16_bits(a);
+  r[1] = (short)bf16_bits(b);
+  r[2] = (short)bf16_bits(c);
+  r[3] = (short)bf16_bits(d);
+  return r;
+}
+__device__ __forceinline__ floatx4 mfma(bf16x4 a, bf16x4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// --------------------------------------------------------------- features
+// Closed-form eigenvalues of a symmetric 3x3 matrix, largest first.
+__device__ void eig3(double a00, double a01, double a02, double a11, double a12, double a22, double e[3]) {
+  const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const double q = (a00 + a11 + a22) / 3.0;
+  const double p2 = (a00 - q) * (a00 - q) + (a11 - q) * (a11 - q) + (a22 - q) * (a22 - q) + 2.0 * p1;
+  if (!(p2 > 0.0)) {
+    e[0] = e[1] = e[2] = q;
+    return;
+  }
+  const double p = sqrt(p2 / 6.0);
+  const double b00 = (a00 - q) / p, b11 = (a11 - q) / p, b22 = (a22 - q) / p;
+  const double b01 = a01 / p, b02 = a02 / p, b12 = a12 / p;
+  const double det = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) + b02 * (b01 * b12 - b11 * b02);
+  const double r = fmin(1.0, fmax(-1.0, 0.5 * det));
+  const double phi = acos(r) / 3.0;
+  e[0] = q + 2.0 * p * cos(phi);
+  e[2] = q + 2.0 * p * cos(phi + 2.0943951023931954923);
+  e[1] = 3.0 * q - e[0] - e[2];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_features(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
+                                                  const int* __restrict__ cell_start, const int* __restrict__ queries,
+                                                  int nq, const int* __restrict__ knn16, float* __restrict__ feats) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int s = queries ? queries[q] : q;
+  const auto pr = rec[s];
+  const double px = pr.x, py = pr.y, pz = pr.z;
+  const int cx = axis_cell(px, G.lo0, G.ih0, G.g0), cy = axis_cell(py, G.lo1, G.ih1, G.g1),
+            cz = axis_cell(pz, G.lo2, G.ih2, G.g2);
+  const double ncells = (double)G.g0 * G.g1 * G.g2;
+  const double nbar = (double)n / ncells;
+  const double vol = (G.hi0 - G.lo0) * (G.hi1 - G.lo1) * (G.hi2 - G.lo2);
+  const double ell = cbrt(vol / (double)n);
+  float f[NF];
+  for (int sc = 0; sc < 3; ++sc) {
+    const int x0 = max(cx - sc, 0), x1 = min(cx + sc, G.g0 - 1);
+    const int y0 = max(cy - sc, 0), y1 = min(cy + sc, G.g1 - 1);
+    const int z0 = max(cz - sc, 0), z1 = min(cz + sc, G.g2 - 1);
+    long long cnt = 0;
+    for (int z = z0; z <= z1; ++z)
+      for (int y = y0; y <= y1; ++y) {
+        const int row = G.g0 * (y + G.g1 * z);
+        cnt += cell_start[row + x1 + 1] - cell_start[row + x0];
+      }
+    const double c = (double)(x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1);
+    f[sc] = (float)log2(1.0 + (double)cnt / (nbar * c));
+  }
+  const int* L = knn16 + (size_t)q * 16;
+  double d[16], ox[16], oy[16], oz[16];
+  int m = 0;
+  for (int i = 0; i < 16; ++i) {
+    const int j = L[i];
+    if (j < 0) break;
+    const auto qr = rec[j];
+    ox[m] = (double)qr.x - px;
+    oy[m] = (double)qr.y - py;
+    oz[m] = (double)qr.z - pz;
+    d[m] = sqrt(ox[m] * ox[m] + oy[m] * oy[m] + oz[m] * oz[m]);
+    ++m;
+  }
+  if (m == 0) {
+    for (int i = 3; i < NF; ++i) f[i] = 0.0f;
+  } else {
+    auto dk = [&](int k) { return d[min(k, m) - 1]; };
+    f[3] = (float)log2(dk(4) / ell);
+    f[4] = (float)log2(dk(8) / ell);
+    f[5] = (float)log2(dk(16) / ell);
+    double mx = 0, my = 0, mz = 0;
+    for (int i = 0; i < m; ++i) {
+      mx += ox[i];
+      my += oy[i];
+      mz += oz[i];
+    }
+    mx /= m;
+    my /= m;
+    mz /= m;
+    f[6] = (float)(sqrt(mx * mx + my * my + mz * mz) / dk(16));
+    f[7] = (float)log2(dk(1) / ell);
+    double c00 = 0, c01 = 0, c02 = 0, c11 = 0, c12 = 0, c22 = 0;
+    for (int i = 0; i < m; ++i) {
+      const double a = ox[i] - mx, b = oy[i] - my, c = oz[i] - mz;
+      c00 += a * a; c01 += a * b; c02 += a * c; c11 += b * b; c12 += b * c; c22 += c * c;
+    }
+    double e[3];
+    eig3(c00 / m, c01 / m, c02 / m, c11 / m, c12 / m, c22 / m, e);
+    const double tr = e[0] + e[1] + e[2];
+    for (int i = 0; i < 3; ++i) f[8 + i] = tr > 0 ? (float)(e[i] / tr) : (float)(1.0 / 3.0);
+    const double wall = fmin(fmin(fmin(px - G.lo0, G.hi0 - px), fmin(py - G.lo1, G.hi1 - py)),
+                             fmin(pz - G.lo2, G.hi2 - pz));
+    f[11] = (float)fmin(wall / dk(16), 4.0);
+  }
+  for (int i = 0; i < NF; ++i) feats[(size_t)q * NF + i] = f[i];
+}
+
+// ------------------------------------------------------------------ network
+struct MlpArgs {
+  const float* theta;
+  const float* norm;
+  const float* feats;
+  const uint8_t* labels;
+  int nb;
+  float inv_batch;
+  float tau;
+  float* partial;   // train: [blocks][NPARAM + 1] (last: loss sum)
+  uint8_t* bucket;  // choose: [nb]
+  float* logits;    // forward: [nb][NO] (nullable)
+};
+
+// mode 0: forward (logits and / or bucket), 1: forward + backward partials
+template <int MODE>
+__global__ __launch_bounds__(64) void k_mlp(MlpArgs a) {
+  const int l = threadIdx.x;
+  const int r = l & 15, g4 = l >> 4;  // A/B: row / column r, k-group g4; D: row 4 g4 + i, column r
+  __shared__ unsigned short hs[16 * NH];  // activations / signals in [sample][unit] (bf16 bits)
+  __shared__ float ps[16 * 16];           // logits -> probabilities [sample][output]
+  const float* th = a.theta;
+  // weights as bf16 operands
+  bf16x4 W1B[4], W2B[4][4], W3B[4], W3T[4], W2T[4][4];
+  for (int nt = 0; nt < 4; ++nt) {  // layer 1: B[k=f][n=u] = W1[u][f]
+    float w[4];
+    for (int i = 0; i < 4; ++i) {
+      const int f = 4 * g4 + i;
+      w[i] = f < NF ? th[OFF_W1 + (16 * nt + r) * NF + f] : 0.0f;
+    }
+    W1B[nt] = pack4(w[0], w[1], w[2], w[3]);
+  }
+  for (int kt = 0; kt < 4; ++kt)
+    for (int nt = 0; nt < 4; ++nt) {  // layer 2: B[k=u1][n=u2] = W2[u2][u1]
+      float w[4], wt[4];
+      for (int i = 0; i < 4; ++i) {
+        w[i] = th[OFF_W2 + (16 * nt + r) * NH + 16 * kt + 4 * g4 + i];
+        wt[i] = th[OFF_W2 + (16 * kt + 4 * g4 + i) * NH + 16 * nt + r];  // backward: B[k=u2][n=u1] = W2[u2][u1]
+      }
+      W2B[kt][nt] = pack4(w[0], w[1], w[2], w[3]);
+      W2T[kt][nt] = pack4(wt[0], wt[1], wt[2], wt[3]);
+    }
+  for (int kt = 0; kt < 4; ++kt) {  // layer 3: B[k=u][n=o] = W3[o][u]
+    float w[4];
+    for (int i = 0; i < 4; ++i) w[i] = r < NO ? th[OFF_W3 + r * NH + 16 * kt + 4 * g4 + i] : 0.0f;
+    W3B[kt] = pack4(w[0], w[1], w[2], w[3]);
+  }
+  for (int nt = 0; nt < 4; ++nt) {  // backward: B[k=o][n=u] = W3[o][u]
+    float w[4];
+    for (int i = 0; i < 4; ++i) {
+      const int o = 4 * g4 + i;
+      w[i] = o < NO ? th[OFF_W3 + o * NH + 16 * nt + r] : 0.0f;
+    }
+    W3T[nt] = pack4(w[0], w[1], w[2], w[3]);
+  }
+  float b1[4], b2[4];
+  for (int nt = 0; nt < 4; ++nt) {
+    b1[nt] = th[OFF_B1 + 16 * nt + r];
+    b2[nt] = th[OFF_B2 + 16 * nt + r];
+  }
+  const float b3 = r < NO ? th[OFF_B3 + r] : 0.0f;
+  float mean[4], sdv[4];
+  for (int i = 0; i < 4; ++i) {
+    const int f = 4 * g4 + i;
+    mean[i] = f < NF ? a.norm[f] : 0.0f;
+    sdv[i] = f < NF ? a.norm[NF + f] : 1.0f;
+  }
+
+  // backward accumulators (D layout)
+  floatx4 gW1[4], gW2[4][4], gW3[4];
+  const floatx4 z4 = {0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 4; ++t) {
+    gW1[t] = z4;
+    gW3[t] = z4;
+    for (int u = 0; u < 4; ++u) gW2[t][u] = z4;
+  }
+  float gb1[4] = {0, 0, 0, 0}, gb2[4] = {0, 0, 0, 0}, gb3 = 0.0f, loss = 0.0f;
+
+  const int tiles_total = (a.nb + 15) / 16;
+  // training: block b owns tiles 4b..4b+3 (its partial sums are per block);
+  // inference: grid-stride over tiles
+  const int t_begin = MODE == 1 ? blockIdx.x * 4 : blockIdx.x;
+  const int t_end = MODE == 1 ? min(tiles_total, blockIdx.x * 4 + 4) : tiles_total;
+  const int t_step = MODE == 1 ? 1 : gridDim.x;
+  for (int tile = t_begin; tile < t_end; tile += t_step) {
+    {
+      const int base = tile * 16;
+      // ---- inputs: A layout X[s=r][f=4 g4 + i]
+      float xa[4];
+      const int sa = base + r;
+      for (int i = 0; i < 4; ++i) {
+        const int f = 4 * g4 + i;
+        const float v = (sa < a.nb && f < NF) ? a.feats[(size_t)sa * NF + f] : 0.0f;
+        xa[i] = (f < NF && sa < a.nb) ? bf16_round((v - mean[i]) / sdv[i]) : 0.0f;
+      }
+      const bf16x4 XA = pack4(xa[0], xa[1], xa[2], xa[3]);
+      // ---- layer 1
+      floatx4 z1[4];
+      bf16x4 H1D[4];
+      for (int nt = 0; nt < 4; ++nt) {
+        z1[nt] = mfma(XA, W1B[nt], z4);
+        float h[4];
+        for (int i = 0; i < 4; ++i) {
+          z1[nt][i] += b1[nt];
+          h[i] = bf16_round(fmaxf(z1[nt][i], 0.0f));
+          hs[(4 * g4 + i) * NH + 16 * nt + r] = bf16_bits(h[i]);
+        }
+        H1D[nt] = pack4(h[0], h[1], h[2], h[3]);
+      }
+      __syncthreads();
+      bf16x4 H1A[4];
+      for (int kt = 0; kt < 4; ++kt) {
+        bf16x4 v;
+        for (int i = 0; i < 4; ++i) v[i] = (short)hs[r * NH + 16 * kt + 4 * g4 + i];
+        H1A[kt] = v;
+      }
+      __syncthreads();
+      // ---- layer 2
+      floatx4 z2[4];
+      bf16x4 H2D[4];
+      for (int nt = 0; nt < 4; ++nt) {
+        floatx4 acc = z4;
+        for (int kt = 0; kt < 4; ++kt) acc = mfma(H1A[kt], W2B[kt][nt], acc);
+        float h[4];
+        for (int i = 0; i < 4; ++i) {
+          acc[i] += b2[nt];
+          h[i] = bf16_round(fmaxf(acc[i], 0.0f));
+          hs[(4 * g4 + i) * NH + 16 * nt + r] = bf16_bits(h[i]);
+        }
+        z2[nt] = acc;
+        H2D[nt] = pack4(h[0], h[1], h[2], h[3]);
+      }
+      __syncthreads();
+      bf16x4 H2A[4];
+      for (int kt = 0; kt < 4; ++kt) {
+        bf16x4 v;
+        for (int i = 0; i < 4; ++i) v[i] = (short)hs[r * NH + 16 * kt + 4 * g4 + i];
+        H2A[kt] = v;
+      }
+      // ---- layer 3: logits D[s = 4 g4 + i][o = r]
+      floatx4 z3 = z4;
+      for (int kt = 0; kt < 4; ++kt) z3 = mfma(H2A[kt], W3B[kt], z3);
+      for (int i = 0; i < 4; ++i) ps[(4 * g4 + i) * 16 + r] = z3[i] + b3;
+      __syncthreads();
+      // ---- softmax per sample (lanes 0..15, one sample each)
+      if (l < 16) {
+        const int s = base + l;
+        float mx = -FLT_MAX;
+        for (int o = 0; o < NO; ++o) mx = fmaxf(mx, ps[l * 16 + o]);
+        float e[NO], sum = 0.0f;
+        for (int o = 0; o < NO; ++o) {
+          e[o] = expf(ps[l * 16 + o] - mx);
+          sum += e[o];
+        }
+        if (MODE == 0 && s < a.nb) {
+          if (a.logits)
+            for (int o = 0; o < NO; ++o) a.logits[(size_t)s * NO + o] = ps[l * 16 + o];
+          if (a.bucket) {
+            float c = 0.0f;
+            int b = NO - 1;
+            for (int o = 0; o < NO - 1; ++o) {
+              c += e[o];
+              if (c >= a.tau * sum) {
+                b = o;
+                break;
+              }
+            }
+            a.bucket[s] = (uint8_t)b;
+          }
+        }
+        if (MODE == 1) {
+          const int y = s < a.nb ? a.labels[s] : 0;
+          if (s < a.nb) loss += ((mx + logf(sum)) - ps[l * 16 + y]) * a.inv_batch;
+          for (int o = 0; o < 16; ++o) {
+            float g = 0.0f;
+            if (o < NO && s < a.nb) g = (e[o] / sum - (o == y ? 1.0f : 0.0f)) * a.inv_batch;
+            ps[l * 16 + o] = g;
+          }
+        }
+      }
+      __syncthreads();
+      if (MODE == 1) {
+        // ---- G3 in D layout [s = 4 g4 + i][o = r]; db3; dW3 += G3^T H2
+        float g3[4];
+        for (int i = 0; i < 4; ++i) g3[i] = ps[(4 * g4 + i) * 16 + r];
+        gb3 += g3[0] + g3[1] + g3[2] + g3[3];
+        const bf16x4 G3D = pack4(g3[0], g3[1], g3[2], g3[3]);
+        for (int nt = 0; nt < 4; ++nt) gW3[nt] = mfma(G3D, H2D[nt], gW3[nt]);
+        // G3 in A layout [s = r][o = 4 g4 + i] (rounded)
+        bf16x4 G3A;
+        for (int i = 0; i < 4; ++i) G3A[i] = (short)bf16_bits(ps[r * 16 + 4 * g4 + i]);
+        // ---- dH2 = G3 W3, G2 = dH2 * (z2 > 0)
+        float g2[4][4];
+        for (int nt = 0; nt < 4; ++nt) {
+          const floatx4 dh = mfma(G3A, W3T[nt], z4);
+          for (int i = 0; i < 4; ++i) {
+            g2[nt][i] = z2[nt][i] > 0.0f ? dh[i] : 0.0f;
+            gb2[nt] += g2[nt][i];
+          }
+        }
+        __syncthreads();
+        bf16x4 G2D[4];
+        for (int nt = 0; nt < 4; ++nt) {
+          G2D[nt] = pack4(g2[nt][0], g2[nt][1], g2[nt][2], g2[nt][3]);
+          for (int i = 0; i < 4; ++i) hs[(4 * g4 + i) * NH + 16 * nt + r] = bf16_bits(g2[nt][i]);
+        }
+        // dW2[u2][u1] += G2^T H1
+        for (int mt = 0; mt < 4; ++mt)
+          for (int nt = 0; nt < 4; ++nt) gW2[mt][nt] = mfma(G2D[mt], H1D[nt], gW2[mt][nt]);
+        __syncthreads();
+        bf16x4 G2A[4];
+        for (int kt = 0; kt < 4; ++kt) {
+          bf16x4 v;
+          for (int i = 0; i < 4; ++i) v[i] = (short)hs[r * NH + 16 * kt + 4 * g4 + i];
+          G2A[kt] = v;
+        }
+        // ---- dH1 = G2 W2, G1 = dH1 * (z1 > 0); dW1 += G1^T X
+        bf16x4 XB;  // B layout X[s = 4 g4 + i][f = r]
+        {
+          float xb[4];
+          for (int i = 0; i < 4; ++i) {
+            const int s = base + 4 * g4 + i;
+            const float v = (s < a.nb && r < NF) ? a.feats[(size_t)s * NF + r] : 0.0f;
+            xb[i] = (s < a.nb && r < NF) ? bf16_round((v - a.norm[r]) / a.norm[NF + r]) : 0.0f;
+          }
+          XB = pack4(xb[0], xb[1], xb[2], xb[3]);
+        }
+        for (int nt = 0; nt < 4; ++nt) {
+          floatx4 dh = z4;
+          for (int kt = 0; kt < 4; ++kt) dh = mfma(G2A[kt], W2T[kt][nt], dh);
+          float g1[4];
+          for (int i = 0; i < 4; ++i) {
+            g1[i] = z1[nt][i] > 0.0f ? dh[i] : 0.0f;
+            gb1[nt] += g1[i];
+          }
+          gW1[nt] = mfma(pack4(g1[0], g1[1], g1[2], g1[3]), XB, gW1[nt]);
+        }
+        __syncthreads();
+      }
+    }
+  }
+  if (MODE == 1) {
+    float* out = a.partial + (size_t)blockIdx.x * (NPARAM + 1);
+    // weights: D layout rows 4 g4 + i, column r
+    for (int mt = 0; mt < 4; ++mt)
+      for (int i = 0; i < 4; ++i) {
+        const int u = 16 * mt + 4 * g4 + i;
+        if (r < NF) out[OFF_W1 + u * NF + r] = gW1[mt][i];
+        for (int nt = 0; nt < 4; ++nt) out[OFF_W2 + u * NH + 16 * nt + r] = gW2[mt][nt][i];
+      }
+    for (int nt = 0; nt < 4; ++nt)
+      for (int i = 0; i < 4; ++i) {
+        const int o = 4 * g4 + i;
+        if (o < NO) out[OFF_W3 + o * NH + 16 * nt + r] = gW3[nt][i];
+      }
+    // biases: reduce over the four row groups
+    for (int nt = 0; nt < 4; ++nt) {
+      float v1 = gb1[nt], v2 = gb2[nt];
+      v1 += __shfl_xor(v1, 16, 64);
+      v1 += __shfl_xor(v1, 32, 64);
+      v2 += __shfl_xor(v2, 16, 64);
+      v2 += __shfl_xor(v2, 32, 64);
+      if (g4 == 0) {
+        out[OFF_B1 + 16 * nt + r] = v1;
+        out[OFF_B2 + 16 * nt + r] = v2;
+      }
+    }
+    float v3 = gb3;
+    v3 += __shfl_xor(v3, 16, 64);
+    v3 += __shfl_xor(v3, 32, 64);
+    if (g4 == 0 && r < NO) out[OFF_B3 + r] = v3;
+    float ls = loss;
+    for (int o = 1; o < 64; o <<= 1) ls += __shfl_xor(ls, o, 64);
+    if (l == 0) out[NPARAM] = ls;
+  }
+}
+
+
+// Fixed-order sum of per-block partials: grads[p] = sum_b partial[b][p].
+__global__ void k_reduce(const float* __restrict__ partial, int blocks, float* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > NPARAM) return;
+  float acc = 0.0f;
+  for (int b = 0; b < blocks; ++b) acc += partial[(size_t)b * (NPARAM + 1) + p];
+  out[p] = acc;
+}
+
+__global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, float lr, float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  const float gi = g[p];
+  const float mi = 0.9f * m[p] + 0.1f * gi;
+  const float vi = 0.999f * v[p] + 0.001f * gi * gi;
+  m[p] = mi;
+  v[p] = vi;
+  theta[p] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+}  // namespace
+
+votess_status run_features(votess_ctx* ctx, const void* sorted, votess_dtype dt, int n, const GridDev& G,
+                           const int32_t* cell_start, const int32_t* queries, int nq, int32_t* knn16, float* feats,
+                           hipStream_t st) {
+  if (nq == 0) return VOTESS_OK;
+  VT_TRY(launch_knn(ctx, sorted, dt, n, G, cell_start, queries, nq, 16, dt == VOTESS_F32 ? VOTESS_F32 : VOTESS_F64,
+                    knn16, st));
+  const unsigned b = (unsigned)((nq + 255) / 256);
+  if (dt == VOTESS_F32)
+    k_features<float><<<b, 256, 0, st>>>((const float4*)sorted, n, G, cell_start, queries, nq, knn16, feats);
+  else
+    k_features<double><<<b, 256, 0, st>>>((const double4*)sorted, n, G, cell_start, queries, nq, knn16, feats);
+  VT_HIP(hipGetLastError());
+  return VOTESS_OK;
+}
+
+votess_status run_choose(votess_kmodel* km, const float* feats, int nq, float tau, uint8_t* bucket, float* logits,
+                         hipStream_t st) {
+  if (nq == 0) return VOTESS_OK;
+  MlpArgs a{};
+  a.theta = km->theta;
+  a.norm = km->norm;
+  a.feats = feats;
+  a.nb = nq;
+  a.tau = tau;
+  a.bucket = bucket;
+  a.logits = logits;
+  const int tiles = (nq + 15) / 16;
+  const int blocks = std::max(1, std::min(tiles, 256 * 16));
+  k_mlp<0><<<blocks, 64, 0, st>>>(a);
+  VT_HIP(hipGetLastError());
+  return VOTESS_OK;
+}
+
+static votess_status run_grad(votess_kmodel* km, const float* feats, const uint8_t* labels, int nb, hipStream_t st) {
+  const int blocks = (nb + kSamplesPerBlock - 1) / kSamplesPerBlock;
+  if (blocks > km->partial_blocks) {
+    dev_free(km->ctx, km->partial);
+    km->partial = (float*)dev_alloc(km->ctx, (size_t)blocks * (NPARAM + 1) * sizeof(float));
+    if (!km->partial) return fail(VOTESS_ENOMEM, "kmodel partial gradients");
+    km->partial_blocks = blocks;
+  }
+  MlpArgs a{};
+  a.theta = km->theta;
+  a.norm = km->norm;
+  a.feats = feats;
+  a.labels = labels;
+  a.nb = nb;
+  a.inv_batch = 1.0f / (float)nb;
+  a.partial = km->partial;
+  k_mlp<1><<<blocks, 64, 0, st>>>(a);
+  VT_HIP(hipGetLastError());
+  k_reduce<<<(NPARAM + 1 + 255) / 256, 256, 0, st>>>(km->partial, blocks, km->grads);
+  VT_HIP(hipGetLastError());
+  return VOTESS_OK;
+}
+
+// Learned first pass of votess_tessellate: 16-NN + features, network choice
+// of a bucket per cell, then per bucket a k-NN pass and a clip pass with the
+// stream phase (cells the list does not certify keep clipping on the GPU).
+votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau, const void* sorted, int n,
+                                 const votess_grid& grid, const int32_t* cell_start, const ClipLaunch& base,
+                                 int32_t*, int32_t* cells_buf, votess_stats& S, hipStream_t st) {
+  const GridDev G = to_dev(grid);
+  const votess_dtype dist = base.knn_dist;
+  void* knn16 = dev_alloc(ctx, (size_t)n * 16 * 4);
+  void* feats = dev_alloc(ctx, (size_t)n * NF * 4);
+  void* bucket = dev_alloc(ctx, (size_t)n);
+  void* knnb = dev_alloc(ctx, (size_t)n * 64 * 4);
+  auto cleanup = [&]() {
+    dev_free(ctx, knn16);
+    dev_free(ctx, feats);
+    dev_free(ctx, bucket);
+    dev_free(ctx, knnb);
+  };
+  if (!knn16 || !feats || !bucket || !knnb) {
+    cleanup();
+    return fail(VOTESS_ENOMEM, "learned pass buffers");
+  }
+  hipEvent_t e0, e1, e2;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipEventCreate(&e2);
+  (void)hipEventRecord(e0, st);
+  votess_status rc = run_features(ctx, sorted, base.dtype, n, G, cell_start, nullptr, n, (int32_t*)knn16,
+                                  (float*)feats, st);
+  (void)hipEventRecord(e1, st);
+  if (rc == VOTESS_OK) rc = run_choose(km, (const float*)feats, n, (float)tau, (uint8_t*)bucket, nullptr, st);
+  (void)hipEventRecord(e2, st);
+  (void)hipEventSynchronize(e2);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  S.ms_features += ms;
+  (void)hipEventElapsedTime(&ms, e1, e2);
+  S.ms_mlp += ms;
+  for (int b = 0; b < NO && rc == VOTESS_OK; ++b) {
+    int cnt = 0;
+    // the compaction takes a status mask; bucket values are 0..6, so bit b selects bucket b
+    rc = launch_compact_failed((const uint8_t*)bucket, nullptr, n, cells_buf, ctx->d_counter,
+                               (uint8_t)(1u << b), st);
+    if (rc != VOTESS_OK) break;
+    if (hipMemcpyAsync(&cnt, ctx->d_counter, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(VOTESS_EHIP, "learned pass: bucket count");
+      break;
+    }
+    S.bucket_cells[b] = cnt;
+    if (cnt == 0) continue;
+    const int k = votess_buckets[b];
+    (void)hipEventRecord(e0, st);
+    rc = launch_knn(ctx, sorted, base.dtype, n, G, cell_start, cells_buf, cnt, k, dist, (int32_t*)knnb, st);
+    (void)hipEventRecord(e1, st);
+    if (rc != VOTESS_OK) break;
+    ClipLaunch c = base;
+    c.cells = cells_buf;
+    c.nc = cnt;
+    c.knn = (const int32_t*)knnb;
+    c.k = k;
+    c.stream = 1;
+    rc = launch_clip(c, st);
+    (void)hipEventRecord(e2, st);
+    (void)hipEventSynchronize(e2);
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    S.ms_knn += ms;
+    (void)hipEventElapsedTime(&ms, e1, e2);
+    S.ms_clip += ms;
+    if (S.npasses < VOTESS_MAX_PASSES) {
+      S.pass_k[S.npasses] = k;
+      S.pass_cells[S.npasses] = cnt;
+      S.pass_failed[S.npasses] = 0;
+      S.npasses++;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  cleanup();
+  return rc;
+}
+
 }  // namespace votess
 
-using votess::fail;
-extern "C" {
-votess_kmodel* votess_kmodel_create(votess_ctx*, uint64_t) { fail(VOTESS_EINVAL, "learned-k is not built yet"); return nullptr; }
-void votess_kmodel_destroy(votess_kmodel*) {}
-votess_status votess_kmodel_set_params(votess_kmodel*, const float*, const float*, const float*) { return fail(VOTESS_EINVAL, "n/a"); }
-votess_status votess_kmodel_get_params(votess_kmodel*, float*, float*, float*) { return fail(VOTESS_EINVAL, "n/a"); }
-votess_status votess_features(votess_ctx*, const void*, int64_t, const votess_grid*, const int32_t*, const int32_t*, int64_t, float*, void*) { return fail(VOTESS_EINVAL, "n/a"); }
-votess_status votess_kmodel_forward(votess_kmodel*, const float*, int64_t, float*, void*) { return fail(VOTESS_EINVAL, "n/a"); }
-votess_status votess_kmodel_grad(votess_kmodel*, const float*, const uint8_t*, int64_t, float*, float*, void*) { return fail(VOTESS_EINVAL, "n/a"); }
-votess_status votess_kmodel_train_step(votess_kmodel*, const float*, const uint8_t*, int64_t, float, float*, void*) { return fail(VOTESS_EINVAL, "n/a"); }
-votess_status votess_kmodel_choose(votess_kmodel*, const float*, int64_t, float, uint8_t*, void*) { return fail(VOTESS_EINVAL, "n/a"); }
+// ------------------------------------------------------------------ C ABI
+using namespace votess;
+
+namespace {
+uint64_t splitmix(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
 }
+}  // namespace
+
+extern "C" {
+
+votess_kmodel* votess_kmodel_create(votess_ctx* ctx, uint64_t seed) {
+  if (!ctx) {
+    fail(VOTESS_EINVAL, "kmodel_create: null ctx");
+    return nullptr;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    fail(VOTESS_EHIP, "kmodel_create: hipSetDevice");
+    return nullptr;
+  }
+  votess_kmodel* km = new votess_kmodel;
+  km->ctx = ctx;
+  km->theta = (float*)dev_alloc(ctx, NPARAM * 4);
+  km->m = (float*)dev_alloc(ctx, NPARAM * 4);
+  km->v = (float*)dev_alloc(ctx, NPARAM * 4);
+  km->norm = (float*)dev_alloc(ctx, 2 * NF * 4);
+  km->grads = (float*)dev_alloc(ctx, (NPARAM + 1) * 4);
+  if (!km->theta || !km->m || !km->v || !km->norm || !km->grads) {
+    votess_kmodel_destroy(km);
+    fail(VOTESS_ENOMEM, "kmodel_create");
+    return nullptr;
+  }
+  // He-uniform weights, zero biases, identity standardisation
+  std::vector<float> th(NPARAM, 0.0f), nm(2 * NF, 0.0f);
+  uint64_t st = seed;
+  auto uni = [&](float lim) { return lim * (2.0f * (float)((splitmix(st) >> 11) * (1.0 / 9007199254740992.0)) - 1.0f); };
+  for (int i = 0; i < NH * NF; ++i) th[OFF_W1 + i] = uni(std::sqrt(6.0f / NF));
+  for (int i = 0; i < NH * NH; ++i) th[OFF_W2 + i] = uni(std::sqrt(6.0f / NH));
+  for (int i = 0; i < NO * NH; ++i) th[OFF_W3 + i] = uni(std::sqrt(6.0f / NH));
+  for (int f = 0; f < NF; ++f) nm[NF + f] = 1.0f;
+  if (hipMemcpy(km->theta, th.data(), NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(km->norm, nm.data(), 2 * NF * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(km->m, 0, NPARAM * 4) != hipSuccess || hipMemset(km->v, 0, NPARAM * 4) != hipSuccess) {
+    votess_kmodel_destroy(km);
+    fail(VOTESS_EHIP, "kmodel_create: upload");
+    return nullptr;
+  }
+  return km;
+}
+
+void votess_kmodel_destroy(votess_kmodel* km) {
+  if (!km) return;
+  votess_ctx* ctx = km->ctx;
+  dev_free(ctx, km->theta);
+  dev_free(ctx, km->m);
+  dev_free(ctx, km->v);
+  dev_free(ctx, km->norm);
+  dev_free(ctx, km->grads);
+  dev_free(ctx, km->partial);
+  delete km;
+}
+
+votess_status votess_kmodel_set_params(votess_kmodel* km, const float* params_h, const float* mean_h,
+                                       const float* std_h) {
+  if (!km) return fail(VOTESS_EINVAL, "kmodel is null");
+  VT_HIP(hipSetDevice(km->ctx->device));
+  if (params_h) {
+    VT_HIP(hipMemcpy(km->theta, params_h, NPARAM * 4, hipMemcpyHostToDevice));
+    VT_HIP(hipMemset(km->m, 0, NPARAM * 4));
+    VT_HIP(hipMemset(km->v, 0, NPARAM * 4));
+    km->step = 0;
+  }
+  if (mean_h) VT_HIP(hipMemcpy(km->norm, mean_h, NF * 4, hipMemcpyHostToDevice));
+  if (std_h) {
+    for (int f = 0; f < NF; ++f)
+      if (!(std_h[f] > 0.0f)) return fail(VOTESS_EINVAL, "kmodel: std must be positive");
+    VT_HIP(hipMemcpy(km->norm + NF, std_h, NF * 4, hipMemcpyHostToDevice));
+  }
+  return VOTESS_OK;
+}
+
+votess_status votess_kmodel_get_params(votess_kmodel* km, float* params_h, float* mean_h, float* std_h) {
+  if (!km) return fail(VOTESS_EINVAL, "kmodel is null");
+  VT_HIP(hipSetDevice(km->ctx->device));
+  VT_HIP(hipDeviceSynchronize());
+  if (params_h) VT_HIP(hipMemcpy(params_h, km->theta, NPARAM * 4, hipMemcpyDeviceToHost));
+  if (mean_h) VT_HIP(hipMemcpy(mean_h, km->norm, NF * 4, hipMemcpyDeviceToHost));
+  if (std_h) VT_HIP(hipMemcpy(std_h, km->norm + NF, NF * 4, hipMemcpyDeviceToHost));
+  return VOTESS_OK;
+}
+
+votess_status votess_features(votess_ctx* ctx, const void* sorted, int64_t n, const votess_grid* grid,
+                              const int32_t* cell_start, const int32_t* queries, int64_t nq, float* feats,
+                              void* stream) {
+  if (!ctx || !grid) return fail(VOTESS_EINVAL, "features: null ctx/grid");
+  if (!queries) nq = n;
+  if (n < 1 || nq < 0 || n >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "features: bad sizes");
+  if (nq > 0 && (!sorted || !cell_start || !feats)) return fail(VOTESS_EINVAL, "features: null buffer");
+  VT_HIP(hipSetDevice(ctx->device));
+  void* knn16 = dev_alloc(ctx, (size_t)std::max<int64_t>(nq, 1) * 16 * 4);
+  if (!knn16) return fail(VOTESS_ENOMEM, "features: 16-NN buffer");
+  hipStream_t st = (hipStream_t)stream;
+  votess_status rc =
+      run_features(ctx, sorted, VOTESS_F32, (int)n, to_dev(*grid), cell_start, queries, (int)nq, (int32_t*)knn16, feats, st);
+  (void)hipStreamSynchronize(st);
+  dev_free(ctx, knn16);
+  return rc;
+}
+
+votess_status votess_kmodel_forward(votess_kmodel* km, const float* feats, int64_t nq, float* logits, void* stream) {
+  if (!km || (nq > 0 && (!feats || !logits))) return fail(VOTESS_EINVAL, "kmodel_forward: null argument");
+  if (nq < 0 || nq >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "kmodel_forward: bad size");
+  VT_HIP(hipSetDevice(km->ctx->device));
+  return run_choose(km, feats, (int)nq, 1.0f, nullptr, logits, (hipStream_t)stream);
+}
+
+votess_status votess_kmodel_choose(votess_kmodel* km, const float* feats, int64_t nq, float tau, uint8_t* bucket,
+                                   void* stream) {
+  if (!km || (nq > 0 && (!feats || !bucket))) return fail(VOTESS_EINVAL, "kmodel_choose: null argument");
+  if (nq < 0 || nq >= (1LL << 31) - 1 || !(tau > 0.0f && tau <= 1.0f))
+    return fail(VOTESS_EINVAL, "kmodel_choose: bad size or tau");
+  VT_HIP(hipSetDevice(km->ctx->device));
+  return run_choose(km, feats, (int)nq, tau, bucket, nullptr, (hipStream_t)stream);
+}
+
+votess_status votess_kmodel_grad(votess_kmodel* km, const float* feats, const uint8_t* labels, int64_t nb,
+                                 float* grads, float* loss, void* stream) {
+  if (!km || !feats || !labels || !grads || !loss) return fail(VOTESS_EINVAL, "kmodel_grad: null argument");
+  if (nb < 1 || nb >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "kmodel_grad: bad batch");
+  VT_HIP(hipSetDevice(km->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  VT_TRY(run_grad(km, feats, labels, (int)nb, st));
+  VT_HIP(hipMemcpyAsync(grads, km->grads, NPARAM * 4, hipMemcpyDeviceToDevice, st));
+  VT_HIP(hipMemcpyAsync(loss, km->grads + NPARAM, 4, hipMemcpyDeviceToDevice, st));
+  return VOTESS_OK;
+}
+
+votess_status votess_kmodel_train_step(votess_kmodel* km, const float* feats, const uint8_t* labels, int64_t nb,
+                                       float lr, float* loss, void* stream) {
+  if (!km || !feats || !labels) return fail(VOTESS_EINVAL, "kmodel_train_step: null argument");
+  if (nb < 1 || nb >= (1LL << 31) - 1 || !(lr > 0.0f)) return fail(VOTESS_EINVAL, "kmodel_train_step: bad batch/lr");
+  VT_HIP(hipSetDevice(km->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  VT_TRY(run_grad(km, feats, labels, (int)nb, st));
+  km->step += 1;
+  const float c1 = 1.0f - std::pow(0.9f, (float)km->step), c2 = 1.0f - std::pow(0.999f, (float)km->step);
+  k_adam<<<(NPARAM + 255) / 256, 256, 0, st>>>(km->theta, km->m, km->v, km->grads, lr, c1, c2);
+  VT_HIP(hipGetLastError());
+  if (loss) VT_HIP(hipMemcpyAsync(loss, km->grads + NPARAM, 4, hipMemcpyDeviceToDevice, st));
+  return VOTESS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+"""GPU parity of the learned-k form: features, BF16 MFMA forward/backward and
+Adam against the FP64 oracle evaluated at the same BF16 rounding points;
+training on the method's own labels; the tessellation is unchanged by the
+network; and what the network gains over the fixed-k method."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import compare_rows, note, volume_errors
+from oracle import features as ofeat
+from oracle import mlp
+from paper_2412_04514_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+vt = pytest.importorskip("paper_2412_04514_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _model(seed=3):
+    from paper_2412_04514_amd import kmodel
+    rng = np.random.default_rng(seed)
+    theta = mlp.init_params(seed) + rng.normal(scale=0.02, size=mlp.NPARAM)
+    mean = rng.normal(size=12)
+    std = rng.uniform(0.5, 2.0, size=12)
+    m = kmodel.KModel(seed=seed)
+    m.set_params(theta.astype(np.float32), mean, std)
+    # the oracle sees exactly the FP32 values the GPU holds
+    return m, theta.astype(np.float32).astype(np.float64), mean.astype(np.float32).astype(np.float64), \
+        std.astype(np.float32).astype(np.float64)
+
+
+def _feats(n, seed=4):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=(n, 12)) * 1.5 + 0.5).astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [16, 1000, 20_011])
+def test_forward_matches_oracle(n):
+    m, theta, mean, std = _model()
+    X = _feats(n)
+    got = m.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    ref, _ = mlp.forward(theta, X.astype(np.float64), mean, std, bf16_points=True)
+    err = np.abs(got - ref)
+    scale = np.abs(ref).max()
+    note(f"  forward n={n}: max abs err {err.max():.2e} (logit scale {scale:.2f})")
+    # FP32 accumulation vs FP64; BF16 rounding of hidden activations may flip by one ulp
+    assert np.percentile(err, 99) <= 2e-3 * scale and err.max() <= 3e-2 * scale
+
+
+@pytest.mark.parametrize("nb", [8192, 1000])
+def test_grad_matches_oracle(nb):
+    m, theta, mean, std = _model(5)
+    X = _feats(nb, 6)
+    y = np.random.default_rng(7).integers(0, 7, nb).astype(np.uint8)
+    g, loss = m.grad(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    lref, gref = mlp.loss_and_grad(theta, X.astype(np.float64), y, mean, std, bf16_points=True)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    note(f"  grad nb={nb}: norm-relative error {rel:.2e}, loss {loss.item():.6f} vs {lref:.6f}")
+    assert rel <= 1e-3
+    assert abs(loss.item() - lref) <= 1e-4 * abs(lref)
+    # per-tensor check too (each block of the flat layout)
+    o = 0
+    for name, shape in mlp.SHAPES:
+        k = int(np.prod(shape))
+        a, b = g[o:o + k], gref[o:o + k]
+        assert np.linalg.norm(a - b) <= 2e-3 * np.linalg.norm(b) + 1e-9, name
+        o += k
+
+
+def test_grad_is_deterministic():
+    m, *_ = _model(8)
+    X = torch.from_numpy(_feats(8192, 9)).cuda()
+    y = torch.from_numpy(np.random.default_rng(10).integers(0, 7, 8192).astype(np.uint8)).cuda()
+    a, _ = m.grad(X, y)
+    b, _ = m.grad(X, y)
+    assert torch.equal(a, b)
+
+
+def test_adam_step_matches_oracle():
+    m, theta, mean, std = _model(11)
+    X = torch.from_numpy(_feats(4096, 12)).cuda()
+    y = torch.from_numpy(np.random.default_rng(13).integers(0, 7, 4096).astype(np.uint8)).cuda()
+    g, _ = m.grad(X, y)
+    m.train_step(X, y, lr=1e-3)
+    new, _, _ = m.get_params()
+    ref, _, _ = mlp.adam_step(theta, g.cpu().numpy().astype(np.float64), np.zeros(mlp.NPARAM),
+                              np.zeros(mlp.NPARAM), 1, lr=1e-3)
+    np.testing.assert_allclose(new, ref, rtol=1e-5, atol=1e-7)
+
+
+def test_choose_matches_oracle():
+    m, theta, mean, std = _model(14)
+    X = _feats(20_000, 15)
+    for tau in (0.5, 0.9):
+        got = m.choose(torch.from_numpy(X).cuda(), tau).cpu().numpy()
+        ref = mlp.choose(theta, X.astype(np.float64), mean, std, tau)
+        assert np.mean(got == ref) >= 0.999
+
+
+@pytest.mark.parametrize("kind", ["uniform", "cluster"])
+def test_features_match_oracle(kind):
+    from paper_2412_04514_amd import kmodel
+    P = getattr(gen, kind)(30_000, seed=16, dtype=np.float32)
+    pts = torch.from_numpy(P).cuda()
+    cs, perm, srt, grid = vt.grid_sort(pts)
+    q = torch.arange(0, len(P), 11, dtype=torch.int32, device="cuda")
+    F = kmodel.features(srt, grid, cs, q).cpu().numpy()
+    rows = perm.cpu().numpy()[q.cpu().numpy()]
+    R = ofeat.features(P.astype(np.float64), rows=rows)
+    err = np.abs(F - R)
+    note(f"  features {kind}: max abs err per feature {np.round(err.max(0), 6).tolist()}")
+    # float distances / ties at the 16th neighbour only move the features slightly
+    assert np.percentile(err, 99.9) <= 1e-3
+    assert np.all(err[:, :3] <= 1e-5)  # grid occupancy is exact
+
+
+@pytest.fixture(scope="module")
+def trained():
+    from paper_2412_04514_amd import kmodel
+    P = gen.cluster(1 << 20, seed=1, dtype=np.float32)
+    m = kmodel.train(torch.from_numpy(P).cuda(), n_train=1 << 18, epochs=4, log=note)
+    return m
+
+
+def test_training_learns(trained):
+    h = trained.history
+    note(f"  training losses {h}  labels {trained.label_hist}")
+    assert h[-1] < h[0]
+    majority = max(trained.label_hist) / sum(trained.label_hist)
+    # cross-entropy of the majority-class guess is the bar to beat
+    p = np.array(trained.label_hist) / sum(trained.label_hist)
+    h_prior = -np.sum(p[p > 0] * np.log(p[p > 0]))
+    assert h[-1] < h_prior, (h[-1], h_prior, majority)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_learned_tessellation_unchanged(trained, prec):
+    P = gen.cluster(200_000, seed=0, dtype=np.float32)
+    res = vt.tessellate(torch.from_numpy(P).cuda(), precision=prec, kmodel=trained, tau=0.9)
+    orc = oracle.tessellate(P.astype(np.float64))
+    assert not compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
+    viol, rel = volume_errors(res.volume.cpu().numpy(), orc["volume"], prec)
+    note(f"  learned {prec}: max rel vol err {rel.max():.2e} buckets {res.stats['bucket_cells']}")
+    assert not viol.any()
+    assert sum(res.stats["bucket_cells"]) == len(P)
+
+
+def test_learned_gain_over_fixed_k(trained):
+    """Same input, same precision: the network's list sizes against fixed k=32
+    with the doubling retry (the method without it)."""
+    from paper_2412_04514_amd import kmodel
+    P = torch.from_numpy(gen.cluster(1 << 20, seed=0, dtype=np.float32)).cuda()
+
+    def timed(**kw):
+        vt.tessellate(P, **kw)
+        torch.cuda.synchronize()
+        best = 1e9
+        for _ in range(3):
+            t = time.perf_counter()
+            r = vt.tessellate(P, **kw)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best, r.stats
+
+    tau, _ = kmodel.tune_tau(trained, torch.from_numpy(gen.cluster(1 << 20, seed=2, dtype=np.float32)).cuda())
+    tl, sl = timed(precision="f32", kmodel=trained, tau=tau)
+    tf, sf = timed(precision="f32", k0=32, max_gpu_retries=1)
+    note(f"  learned (tau {tau}) {tl * 1e3:.1f} ms vs fixed-k {tf * 1e3:.1f} ms: gain x{tf / tl:.2f}; "
+         f"learned knn+clip {sl['ms_knn'] + sl['ms_clip'] + sl['ms_features'] + sl['ms_mlp']:.1f} ms, "
+         f"fixed {sf['ms_knn'] + sf['ms_clip']:.1f} ms")
+    assert tl < tf
