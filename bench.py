@@ -51,6 +51,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-baseline-f64", action="store_true")
     ap.add_argument("--mode", choices=["auto", "fixed", "learned"], default="auto")
     ap.add_argument("--k0", type=int, default=32)
+    ap.add_argument("--profile-step", action="store_true", help="one headline step only (for rocprofv3)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the tessellation has no multi-GPU path here.",
@@ -102,6 +103,9 @@ def main(argv=None) -> int:
         return ms, stats
 
     ms, stats = run(headline, args.steps, args.warmup, label)
+    if args.profile_step:
+        log(f"[bench] profile step done: {stats[-1]}")
+        return 0
     mean = lambda key: float(np.mean([s[key] for s in stats]))  # noqa: E731
     st0 = stats[-1]
     ms_sort, ms_knn, ms_clip = mean("ms_sort"), mean("ms_knn"), mean("ms_clip")

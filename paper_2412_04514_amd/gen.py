@@ -158,6 +158,7 @@ WORKLOADS = {
     "uniform-1m-f32": (uniform, 1 << 20, np.float32),
     "cluster-4m-f32": (cluster, 1 << 22, np.float32),
     "cluster-16m-f32": (cluster, 1 << 24, np.float32),
+    "uniform-16m-f32": (uniform, 1 << 24, np.float32),
     "filament-64m-f32": (filament, 1 << 26, np.float32),
 }
 
