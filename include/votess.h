@@ -126,17 +126,36 @@ VOTESS_API votess_status votess_grid_plan(int64_t n, const votess_box* box, doub
  *   perm       [n] int32 out: perm[s] = original index of sorted point s
  *   sorted     [n,4] of dtype out: (x, y, z, id) where id is the original
  *              index stored as the bit pattern of an int32 (F32) / int64 (F64)
- * Within a grid cell points keep ascending original index (deterministic).
- * Requires n < 2^31.  Points outside the box raise device error bit 1. */
+ *   subinfo    [2*ncells] int32 out (nullable): sub-grids of dense cells.  A
+ *              cell with more than 16 points gets a sub-grid over the
+ *              bounding box [lo, lo + e] of its points: m0 x m1 x m2 sub-cells,
+ *              m_a = max(1, floor(e_a s)), s = cbrt((count/2) / (e0 e1 e2)),
+ *              then the largest m_a lowered until m0 m1 m2 <= count/2; a
+ *              point's sub-cell is s_a = clamp(floor((x_a - lo_a) ih_a), 0,
+ *              m_a - 1), ih_a = m_a / e_a, id s0 + m0 (s1 + m1 s2).
+ *              subinfo[2c] = offset of the cell's record in sub_start (-1
+ *              for other cells), subinfo[2c+1] = m0 m1 m2
+ *   sub_start  [votess_sub_capacity(n)] int32 out (nullable with subinfo),
+ *              16-byte aligned: per dense cell a record at its offset (a
+ *              multiple of 4): m0, m1, m2, 0, then lo[3] and ih[3] as doubles,
+ *              then the m0 m1 m2 + 1 sub-cell starts relative to cell_start[c]
+ * Within a cell points are ordered by ascending original index; with
+ * subinfo, a dense cell's points are ordered by (sub-cell, original index).
+ * Deterministic.  Requires n < 2^31.  Points outside the box raise device
+ * error bit 1. */
 VOTESS_API votess_status votess_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dtype, int64_t n,
                                const votess_box* box, const votess_grid* grid, int32_t* cell_start,
-                               int32_t* perm, void* sorted, void* stream);
+                               int32_t* perm, void* sorted, int32_t* subinfo, int32_t* sub_start, void* stream);
+
+/* Entries (int32) sub_start needs for n points: n/2 + 20n/17 + 1024. */
+VOTESS_API int64_t votess_sub_capacity(int64_t n);
 
 /* ------------------------------------------------------------- k-NN (a4) */
 
 /* The k nearest other points of each query (paper, Summary: "a k-nearest
  * neighbors search is performed"), by a shell-expanding search over the grid.
- *   sorted, cell_start  from votess_grid_sort
+ *   sorted, cell_start, subinfo, sub_start  from votess_grid_sort (the last
+ *              two nullable: dense cells are then scanned whole)
  *   queries    [nq] sorted indices, or NULL for all n points (nq = n)
  *   dist       arithmetic of the squared distances: F64, or F32 (F32 input only)
  *   knn        [nq,k] int32 out: sorted indices ascending by (d^2, sorted index),
@@ -144,8 +163,9 @@ VOTESS_API votess_status votess_grid_sort(votess_ctx* ctx, const void* pts, vote
  * k is one of 8, 12, 16, 24, 32, 48, 64.  A zero distance raises device error
  * bit 2 (duplicate). */
 VOTESS_API votess_status votess_knn(votess_ctx* ctx, const void* sorted, votess_dtype dtype, int64_t n,
-                         const votess_grid* grid, const int32_t* cell_start, const int32_t* queries, int64_t nq,
-                         int32_t k, votess_dtype dist, int32_t* knn, void* stream);
+                         const votess_grid* grid, const int32_t* cell_start, const int32_t* subinfo,
+                         const int32_t* sub_start, const int32_t* queries, int64_t nq, int32_t k, votess_dtype dist,
+                         int32_t* knn, void* stream);
 
 /* ------------------------------------------------------- clipping (a6) */
 
@@ -161,6 +181,8 @@ typedef struct {
                                  rings (unbounded k); needs k-lists in the clip precision */
   const votess_grid* grid;    /* stream only: the grid of votess_grid_sort */
   const int32_t* cell_start;  /* stream only: [ncells+1] from votess_grid_sort */
+  const int32_t* subinfo;     /* stream only, nullable: sub-grids from votess_grid_sort */
+  const int32_t* sub_start;
 } votess_clip_opts;
 
 /* Clips the box by the bisectors of each cell's k-list, nearest first, and
@@ -269,8 +291,8 @@ VOTESS_API votess_status votess_kmodel_get_params(votess_kmodel* m, float* param
 /* Features of each query from a 16-NN pass: 12 floats per query (see the
  * design notes for the definitions).  F32 sorted input only. */
 VOTESS_API votess_status votess_features(votess_ctx* ctx, const void* sorted, int64_t n, const votess_grid* grid,
-                              const int32_t* cell_start, const int32_t* queries, int64_t nq, float* feats,
-                              void* stream);
+                              const int32_t* cell_start, const int32_t* subinfo, const int32_t* sub_start,
+                              const int32_t* queries, int64_t nq, float* feats, void* stream);
 
 /* logits [nq,7] float = network(standardised feats). */
 VOTESS_API votess_status votess_kmodel_forward(votess_kmodel* m, const float* feats, int64_t nq, float* logits, void* stream);

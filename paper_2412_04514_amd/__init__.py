@@ -118,9 +118,34 @@ def grid_plan(n: int, box=((0, 0, 0), (1, 1, 1)), pts_per_cell: float = 2.0) -> 
     return g
 
 
+class GridIndex:
+    """The grid of a sort (``.c``: the C struct) and its dense-cell sub-grids."""
+
+    def __init__(self, c: _lib.Grid, subinfo=None, sub_start=None):
+        self.c = c
+        self.subinfo = subinfo
+        self.sub_start = sub_start
+
+    g = property(lambda self: self.c.g)
+    lo = property(lambda self: self.c.lo)
+    hi = property(lambda self: self.c.hi)
+    inv_h = property(lambda self: self.c.inv_h)
+    ncells = property(lambda self: self.c.ncells)
+
+
+def _grid_c(grid):
+    return grid.c if isinstance(grid, GridIndex) else grid
+
+
+def _sub(grid):
+    if isinstance(grid, GridIndex) and grid.subinfo is not None:
+        return _ptr(grid.subinfo), _ptr(grid.sub_start)
+    return None, None
+
+
 def grid_sort(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), grid: _lib.Grid | None = None,
-              pts_per_cell: float = 2.0, ctx: Context | None = None):
-    """Counting sort into the grid: returns (cell_start, perm, sorted[n,4], grid)."""
+              pts_per_cell: float = 2.0, subgrids: bool = True, ctx: Context | None = None):
+    """Counting sort into the grid: returns (cell_start, perm, sorted[n,4], GridIndex)."""
     ctx = ctx or Context.get()
     pts = points.contiguous()
     n = pts.shape[0]
@@ -129,10 +154,15 @@ def grid_sort(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), grid: _lib.Grid 
     cell_start = torch.empty(grid.ncells + 1, dtype=torch.int32, device=dev)
     perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
     sorted_ = torch.empty(max(n, 1), 4, dtype=pts.dtype, device=dev)
+    subinfo = sub_start = None
+    if subgrids:
+        subinfo = torch.empty(2 * grid.ncells, dtype=torch.int32, device=dev)
+        sub_start = torch.empty(ctx.lib.votess_sub_capacity(n), dtype=torch.int32, device=dev)
     b = _box(box)
     check(ctx.lib.votess_grid_sort(ctx.handle, _ptr(pts), _dtype_code(pts), n, C.byref(b), C.byref(grid),
-                                   _ptr(cell_start), _ptr(perm), _ptr(sorted_), _stream()))
-    return cell_start, perm[:n], sorted_[:n], grid
+                                   _ptr(cell_start), _ptr(perm), _ptr(sorted_), _ptr(subinfo), _ptr(sub_start),
+                                   _stream()))
+    return cell_start, perm[:n], sorted_[:n], GridIndex(grid, subinfo, sub_start)
 
 
 def knn(sorted_: torch.Tensor, grid: _lib.Grid, cell_start: torch.Tensor, k: int, queries=None,
@@ -142,8 +172,10 @@ def knn(sorted_: torch.Tensor, grid: _lib.Grid, cell_start: torch.Tensor, k: int
     n = sorted_.shape[0]
     nq = n if queries is None else queries.shape[0]
     out = torch.empty(max(nq, 1), k, dtype=torch.int32, device=sorted_.device)
-    check(ctx.lib.votess_knn(ctx.handle, _ptr(sorted_), _dtype_code(sorted_), n, C.byref(grid), _ptr(cell_start),
-                             _ptr(queries), nq, int(k), F32 if dist == "f32" else F64, _ptr(out), _stream()))
+    si, ss = _sub(grid)
+    check(ctx.lib.votess_knn(ctx.handle, _ptr(sorted_), _dtype_code(sorted_), n, C.byref(_grid_c(grid)),
+                             _ptr(cell_start), si, ss, _ptr(queries), nq, int(k), F32 if dist == "f32" else F64,
+                             _ptr(out), _stream()))
     return out[:nq]
 
 
@@ -180,8 +212,12 @@ def clip_cells(sorted_: torch.Tensor, knn_: torch.Tensor, k: int, box=((0, 0, 0)
     o.out_by_id = 0
     o.stream = int(bool(stream))
     if stream:
-        o.grid = C.cast(C.pointer(grid), C.c_void_p)
+        gc = _grid_c(grid)
+        o.grid = C.cast(C.pointer(gc), C.c_void_p)
         o.cell_start = cell_start.data_ptr()
+        si, ss = _sub(grid)
+        o.subinfo = si.value if si is not None else None
+        o.sub_start = ss.value if ss is not None else None
     b = _box(box)
     check(ctx.lib.votess_clip_cells(ctx.handle, _ptr(sorted_), _dtype_code(sorted_), n, C.byref(b), _ptr(cells), nc,
                                     _ptr(knn_), int(k), C.byref(o), _ptr(out["status"]), _ptr(out["nbr_count"]),

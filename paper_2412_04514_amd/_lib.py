@@ -30,7 +30,8 @@ class Grid(C.Structure):
 class ClipOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("eps", C.c_double), ("knn_dist", C.c_int), ("max_nbr", C.c_int32),
                 ("max_vert", C.c_int32), ("capacity", C.c_int32), ("out_by_id", C.c_int32),
-                ("stream", C.c_int32), ("grid", C.c_void_p), ("cell_start", C.c_void_p)]
+                ("stream", C.c_int32), ("grid", C.c_void_p), ("cell_start", C.c_void_p),
+                ("subinfo", C.c_void_p), ("sub_start", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -83,8 +84,9 @@ SIGNATURES = {
     "votess_set_allocator": (None, [P, ALLOC_FN, RELEASE_FN, P]),
     "votess_ctx_errors": (C.c_int, [P, P, C.POINTER(C.c_uint32)]),
     "votess_grid_plan": (C.c_int, [i64, C.POINTER(Box), C.c_double, C.POINTER(Grid)]),
-    "votess_grid_sort": (C.c_int, [P, P, C.c_int, i64, C.POINTER(Box), C.POINTER(Grid), P, P, P, P]),
-    "votess_knn": (C.c_int, [P, P, C.c_int, i64, C.POINTER(Grid), P, P, i64, i32, C.c_int, P, P]),
+    "votess_grid_sort": (C.c_int, [P, P, C.c_int, i64, C.POINTER(Box), C.POINTER(Grid), P, P, P, P, P, P]),
+    "votess_sub_capacity": (i64, [i64]),
+    "votess_knn": (C.c_int, [P, P, C.c_int, i64, C.POINTER(Grid), P, P, P, P, i64, i32, C.c_int, P, P]),
     "votess_clip_cells": (C.c_int, [P, P, C.c_int, i64, C.POINTER(Box), P, i64, P, i32, C.POINTER(ClipOpts),
                                     P, P, P, P, P, P, P, P, P]),
     "votess_params_default": (None, [C.POINTER(Params)]),
@@ -94,7 +96,7 @@ SIGNATURES = {
     "votess_kmodel_destroy": (None, [P]),
     "votess_kmodel_set_params": (C.c_int, [P, P, P, P]),
     "votess_kmodel_get_params": (C.c_int, [P, P, P, P]),
-    "votess_features": (C.c_int, [P, P, i64, C.POINTER(Grid), P, P, i64, P, P]),
+    "votess_features": (C.c_int, [P, P, i64, C.POINTER(Grid), P, P, P, P, i64, P, P]),
     "votess_kmodel_forward": (C.c_int, [P, P, i64, P, P]),
     "votess_kmodel_grad": (C.c_int, [P, P, P, i64, P, P, P]),
     "votess_kmodel_train_step": (C.c_int, [P, P, P, i64, C.c_float, P, P]),

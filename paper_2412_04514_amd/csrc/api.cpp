@@ -53,6 +53,16 @@ votess_status Workspace::reserve(size_t bytes) {
   return VOTESS_OK;
 }
 
+// sub-grid buffers: both or neither, records read as 16-byte vectors
+votess_status check_sub(const int32_t* subinfo, const int32_t* sub_start, int64_t n, const char* where) {
+  if ((subinfo == nullptr) != (sub_start == nullptr))
+    return fail(VOTESS_EINVAL, "%s: subinfo and sub_start go together", where);
+  if (sub_start && ((uintptr_t)sub_start & 15u))
+    return fail(VOTESS_EINVAL, "%s: sub_start must be 16-byte aligned", where);
+  if (subinfo && sub_capacity(n) > INT32_MAX) return fail(VOTESS_EINVAL, "%s: n too large for sub-grids", where);
+  return VOTESS_OK;
+}
+
 namespace {
 
 struct Buf {  // owned device buffer from the context allocator
@@ -213,15 +223,19 @@ static votess_status check_grid(const votess_grid* g) {
   return VOTESS_OK;
 }
 
+int64_t votess_sub_capacity(int64_t n) { return sub_capacity(n < 0 ? 0 : n); }
+
+
 votess_status votess_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dtype, int64_t n,
                                const votess_box* box, const votess_grid* grid, int32_t* cell_start, int32_t* perm,
-                               void* sorted, void* stream) {
+                               void* sorted, int32_t* subinfo, int32_t* sub_start, void* stream) {
   if (!ctx) return fail(VOTESS_EINVAL, "ctx is null");
   VT_TRY(check_box(box));
   VT_TRY(check_grid(grid));
   if (n < 0 || n >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "grid_sort: n out of range");
   if (n > 0 && (!pts || !perm || !sorted)) return fail(VOTESS_EINVAL, "grid_sort: null buffer");
   if (!cell_start) return fail(VOTESS_EINVAL, "grid_sort: null cell_start");
+  VT_TRY(check_sub(subinfo, sub_start, n, "grid_sort"));
   if (dtype != VOTESS_F32 && dtype != VOTESS_F64) return fail(VOTESS_EINVAL, "bad dtype");
   VT_HIP(hipSetDevice(ctx->device));
   VT_TRY(ctx->ws.reserve(grid_sort_workspace(n, grid->ncells)));
@@ -230,13 +244,14 @@ votess_status votess_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dt
     g2.lo[a] = box->lo[a];
     g2.hi[a] = box->hi[a];
   }
-  return launch_grid_sort(ctx, pts, dtype, (int)n, to_dev(g2), grid->ncells, cell_start, perm, sorted, ctx->ws,
-                          (hipStream_t)stream);
+  return launch_grid_sort(ctx, pts, dtype, (int)n, to_dev(g2), grid->ncells, cell_start, perm, sorted, subinfo,
+                          sub_start, ctx->ws, (hipStream_t)stream);
 }
 
 votess_status votess_knn(votess_ctx* ctx, const void* sorted, votess_dtype dtype, int64_t n,
-                         const votess_grid* grid, const int32_t* cell_start, const int32_t* queries, int64_t nq,
-                         int32_t k, votess_dtype dist, int32_t* knn, void* stream) {
+                         const votess_grid* grid, const int32_t* cell_start, const int32_t* subinfo,
+                         const int32_t* sub_start, const int32_t* queries, int64_t nq, int32_t k, votess_dtype dist,
+                         int32_t* knn, void* stream) {
   if (!ctx) return fail(VOTESS_EINVAL, "ctx is null");
   VT_TRY(check_grid(grid));
   if (!valid_k(k)) return fail(VOTESS_EINVAL, "knn: k=%d not in {8,12,16,24,32,48,64}", k);
@@ -244,7 +259,11 @@ votess_status votess_knn(votess_ctx* ctx, const void* sorted, votess_dtype dtype
   if (n < 0 || nq < 0 || n >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "knn: bad sizes");
   if (nq > 0 && (!sorted || !cell_start || !knn)) return fail(VOTESS_EINVAL, "knn: null buffer");
   VT_HIP(hipSetDevice(ctx->device));
-  return launch_knn(ctx, sorted, dtype, (int)n, to_dev(*grid), cell_start, queries, (int)nq, k, dist, knn,
+  VT_TRY(check_sub(subinfo, sub_start, n, "knn"));
+  SubGrid sg;
+  sg.info = (const int2*)subinfo;
+  sg.start = sub_start;
+  return launch_knn(ctx, sorted, dtype, (int)n, to_dev(*grid), cell_start, sg, queries, (int)nq, k, dist, knn,
                     (hipStream_t)stream);
 }
 
@@ -299,6 +318,9 @@ votess_status votess_clip_cells(votess_ctx* ctx, const void* sorted, votess_dtyp
     VT_TRY(check_grid(opts->grid));
     a.grid = to_dev(*opts->grid);
     a.cell_start = opts->cell_start;
+    VT_TRY(check_sub(opts->subinfo, opts->sub_start, n, "clip"));
+    a.sub.info = (const int2*)opts->subinfo;
+    a.sub.start = opts->sub_start;
   }
   return launch_clip(a, (hipStream_t)stream);
 }
@@ -389,8 +411,11 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   const votess_dtype dist = P.precision == VOTESS_CLIP_F32_RECHECK ? VOTESS_F32 : VOTESS_F64;
 
   Buf cell_start, perm, sorted, status, nbr_count, nbr, vol, vcount, verts, vplanes, knn, cells, cells2, counters;
+  Buf subinfo, sub_start;
   const size_t nn = (size_t)std::max(n, 1);
   VT_TRY(alloc_buf(ctx, cell_start, (grid.ncells + 1) * 4));
+  VT_TRY(alloc_buf(ctx, subinfo, grid.ncells * 8));
+  VT_TRY(alloc_buf(ctx, sub_start, (size_t)sub_capacity(n) * 4));
   VT_TRY(alloc_buf(ctx, perm, nn * 4));
   VT_TRY(alloc_buf(ctx, sorted, nn * 4 * esz));
   VT_TRY(alloc_buf(ctx, status, nn));
@@ -413,7 +438,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   {
     Timer T(st, &S.ms_sort);
     VT_TRY(votess_grid_sort(ctx, pts, dtype, n, box, &grid, cell_start.get<int32_t>(), perm.get<int32_t>(),
-                            sorted.p, stream));
+                            sorted.p, subinfo.get<int32_t>(), sub_start.get<int32_t>(), stream));
   }
   uint32_t errs = 0;
   VT_TRY(votess_ctx_errors(ctx, stream, &errs));
@@ -446,6 +471,9 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   const GridDev GD = to_dev(grid);
   base.grid = GD;
   base.cell_start = cell_start.get<int32_t>();
+  base.sub.info = subinfo.get<int2>();
+  base.sub.start = sub_start.get<int32_t>();
+  const SubGrid SG = base.sub;
   // the last list pass on the GPU streams uncertified cells on by grid rings
   const bool stream_last = P.gpu_stream != 0 && P.force_fail_every == 0;
   int nretry = 0;
@@ -465,7 +493,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
       VT_TRY(alloc_buf(ctx, knn, nn * (size_t)k * 4));
       {
         Timer T(st, &S.ms_knn);
-        VT_TRY(launch_knn(ctx, sorted.p, dtype, n, GD, cell_start.get<int32_t>(), nullptr, n, k, dist,
+        VT_TRY(launch_knn(ctx, sorted.p, dtype, n, GD, cell_start.get<int32_t>(), SG, nullptr, n, k, dist,
                           knn.get<int32_t>(), st));
       }
       {
@@ -508,7 +536,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     VT_TRY(alloc_buf(ctx, knn2, (size_t)ncap * kk * 4));
     {
       Timer T(st, &S.ms_knn);
-      VT_TRY(launch_knn(ctx, sorted.p, dtype, n, GD, cell_start.get<int32_t>(), nxt, ncap, kk, dist,
+      VT_TRY(launch_knn(ctx, sorted.p, dtype, n, GD, cell_start.get<int32_t>(), SG, nxt, ncap, kk, dist,
                         knn2.get<int32_t>(), st));
     }
     Timer T(st, &S.ms_clip);
@@ -526,7 +554,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     VT_TRY(alloc_buf(ctx, knn, (size_t)nfail * k * 4));
     {
       Timer T(st, &S.ms_knn);
-      VT_TRY(launch_knn(ctx, sorted.p, dtype, n, GD, cell_start.get<int32_t>(), cur, nfail, k, dist,
+      VT_TRY(launch_knn(ctx, sorted.p, dtype, n, GD, cell_start.get<int32_t>(), SG, cur, nfail, k, dist,
                         knn.get<int32_t>(), st));
     }
     {

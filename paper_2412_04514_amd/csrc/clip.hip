@@ -64,6 +64,7 @@ struct ClipArgs {
   int stream;
   const int* cell_start;
   GridDev grid;
+  SubGrid sub;  // sub-grids of dense cells (info null: none)
 };
 
 template <typename R>
@@ -607,6 +608,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     }
     // flower box in grid cells, from the current vertices (group reduction)
     int fb0 = 0, fb1 = -1, fb2 = 0, fb3 = -1, fb4 = 0, fb5 = -1;
+    double fw0 = 0, fw1 = 0, fw2 = 0, fw3 = 0, fw4 = 0, fw5 = 0;  // the same box in coordinates
     auto flower_box = [&]() {
       double mn0 = 1e300, mn1 = 1e300, mn2 = 1e300, mx0 = -1e300, mx1 = -1e300, mx2 = -1e300;
       for (int t = j; t < H; t += L) {
@@ -623,15 +625,24 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
         mn1 = fmin(mn1, shfl_xor_w(mn1, o, L)); mx1 = fmax(mx1, shfl_xor_w(mx1, o, L));
         mn2 = fmin(mn2, shfl_xor_w(mn2, o, L)); mx2 = fmax(mx2, shfl_xor_w(mx2, o, L));
       }
-      fb0 = axis_cell(p64x + mn0 - gmarg, Gd.lo0, Gd.ih0, Gd.g0);
-      fb1 = axis_cell(p64x + mx0 + gmarg, Gd.lo0, Gd.ih0, Gd.g0);
-      fb2 = axis_cell(p64y + mn1 - gmarg, Gd.lo1, Gd.ih1, Gd.g1);
-      fb3 = axis_cell(p64y + mx1 + gmarg, Gd.lo1, Gd.ih1, Gd.g1);
-      fb4 = axis_cell(p64z + mn2 - gmarg, Gd.lo2, Gd.ih2, Gd.g2);
-      fb5 = axis_cell(p64z + mx2 + gmarg, Gd.lo2, Gd.ih2, Gd.g2);
+      fw0 = p64x + mn0 - gmarg; fw1 = p64x + mx0 + gmarg;
+      fw2 = p64y + mn1 - gmarg; fw3 = p64y + mx1 + gmarg;
+      fw4 = p64z + mn2 - gmarg; fw5 = p64z + mx2 + gmarg;
+      fb0 = axis_cell(fw0, Gd.lo0, Gd.ih0, Gd.g0);
+      fb1 = axis_cell(fw1, Gd.lo0, Gd.ih0, Gd.g0);
+      fb2 = axis_cell(fw2, Gd.lo1, Gd.ih1, Gd.g1);
+      fb3 = axis_cell(fw3, Gd.lo1, Gd.ih1, Gd.g1);
+      fb4 = axis_cell(fw4, Gd.lo2, Gd.ih2, Gd.g2);
+      fb5 = axis_cell(fw5, Gd.lo2, Gd.ih2, Gd.g2);
     };
     int rr = -1, zz = 0, yy = 0, part = 0, zhi = -1, ylo = 0, yhi = -1;
     int jcur = 0, jend = 0;
+    // the x-run being split at dense cells, and the sub-block of the dense
+    // cell being scanned (sub-cells that meet the flower box)
+    int rx = 1, rx1 = 0, rrow = 0;
+    int dm = 0, dm0 = 0, dm1 = 0, dbase = 0, dsx0 = 0, dsx1 = -1, dsy0 = 0, dsy1 = -1, dsz0 = 0, dsz1 = -1;
+    int dq0 = 0, dq1 = 0, dq2 = 0, drs = -1, dz = 1, dzhi = 0, dy = 0, dylo = 0, dyhi = -1, dpart = 0;
+    const int* dst = nullptr;
     unsigned pend = 0;
     int myj = -1;
     R myd2 = R(0);
@@ -643,9 +654,88 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
         bool done = false;
         while (!done) {
           if (jcur >= jend) {
-            // next run of the ring: one contiguous x-range of grid cells
+            // next contiguous range of points: a sub-cell x-run of a dense
+            // cell, a stretch of sparse cells of the current x-run, or the
+            // ring's next x-run of grid cells
             bool have_run = false;
             while (!have_run) {
+              if (dm > 0) {
+                // sub-rings around the sub-cell nearest the seed, inside the
+                // sub-block: nearer sub-cells first
+                if (dz > dzhi) {
+                  if (drs >= 0 && dq0 - drs <= dsx0 && dq0 + drs >= dsx1 && dq1 - drs <= dsy0 && dq1 + drs >= dsy1 &&
+                      dq2 - drs <= dsz0 && dq2 + drs >= dsz1) {
+                    dm = 0;
+                    continue;
+                  }
+                  ++drs;
+                  dz = max(dq2 - drs, dsz0);
+                  dzhi = min(dq2 + drs, dsz1);
+                  dylo = max(dq1 - drs, dsy0);
+                  dyhi = min(dq1 + drs, dsy1);
+                  dy = dylo;
+                  dpart = 0;
+                  if (dylo > dyhi) dz = dzhi + 1;
+                  continue;
+                }
+                const bool sface = dz == dq2 - drs || dz == dq2 + drs || dy == dq1 - drs || dy == dq1 + drs;
+                int sx0 = 1, sx1 = 0;
+                if (dpart == 0) {
+                  if (sface) { sx0 = max(dq0 - drs, dsx0); sx1 = min(dq0 + drs, dsx1); }
+                  else if (dq0 - drs >= dsx0) { sx0 = sx1 = dq0 - drs; }
+                  dpart = 1;
+                } else if (dpart == 1) {
+                  if (!sface && drs > 0 && dq0 + drs <= dsx1) { sx0 = sx1 = dq0 + drs; }
+                  dpart = 2;
+                } else {
+                  dpart = 0;
+                  if (++dy > dyhi) { dy = dylo; ++dz; }
+                  continue;
+                }
+                if (sx0 <= sx1) {
+                  const int rowb = kSubHead + dm0 * (dy + dm1 * dz);
+                  jcur = dbase + dst[rowb + sx0];
+                  jend = dbase + dst[rowb + sx1 + 1];
+                  have_run = jcur < jend;
+                }
+                continue;
+              }
+              if (rx <= rx1) {
+                int xe = rx1 + 1;
+                if (a.sub.info) {
+                  xe = rx;
+                  while (xe <= rx1 && a.sub.info[rrow + xe].x < 0) ++xe;
+                }
+                if (xe > rx) {
+                  jcur = a.cell_start[rrow + rx];
+                  jend = a.cell_start[rrow + xe];
+                  rx = xe;
+                  have_run = jcur < jend;
+                  continue;
+                }
+                // dense cell rx: its sub-cells inside the flower box
+                const int2 info = a.sub.info[rrow + rx];
+                const SubCell sc = sub_cell(a.sub.start + info.x);
+                dsx0 = sub_axis(fw0, sc.lo0, sc.ih0, sc.m0);
+                dsx1 = sub_axis(fw1, sc.lo0, sc.ih0, sc.m0);
+                dsy0 = sub_axis(fw2, sc.lo1, sc.ih1, sc.m1);
+                dsy1 = sub_axis(fw3, sc.lo1, sc.ih1, sc.m1);
+                dsz0 = sub_axis(fw4, sc.lo2, sc.ih2, sc.m2);
+                dsz1 = sub_axis(fw5, sc.lo2, sc.ih2, sc.m2);
+                dq0 = min(max(sub_axis(p64x, sc.lo0, sc.ih0, sc.m0), dsx0), dsx1);
+                dq1 = min(max(sub_axis(p64y, sc.lo1, sc.ih1, sc.m1), dsy0), dsy1);
+                dq2 = min(max(sub_axis(p64z, sc.lo2, sc.ih2, sc.m2), dsz0), dsz1);
+                drs = -1;
+                dz = 1;
+                dzhi = 0;
+                dst = a.sub.start + info.x;
+                dbase = a.cell_start[rrow + rx];
+                dm = 1;
+                dm0 = sc.m0;
+                dm1 = sc.m1;
+                ++rx;
+                continue;
+              }
               if (rr < 0 || zz > zhi) {
                 // ring rr finished (or none yet): final when the block contains the flower box
                 flower_box();
@@ -679,10 +769,9 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
                 continue;
               }
               if (x0 <= x1) {
-                const int row = Gd.g0 * (yy + Gd.g1 * zz);
-                jcur = a.cell_start[row + x0];
-                jend = a.cell_start[row + x1 + 1];
-                have_run = jcur < jend;
+                rrow = Gd.g0 * (yy + Gd.g1 * zz);
+                rx = x0;
+                rx1 = x1;
               }
             }
             if (done) break;
@@ -900,6 +989,7 @@ votess_status launch_clip(const ClipLaunch& a, hipStream_t st) {
   c.stream = a.stream;
   c.cell_start = a.cell_start;
   c.grid = a.grid;
+  c.sub = a.sub;
   const bool f32 = a.precision == VOTESS_CLIP_F32_RECHECK;
   if (f32 && a.dtype != VOTESS_F32) return fail(VOTESS_EINVAL, "clip: F32_RECHECK needs F32 positions");
   if (a.stream && (a.knn_dist == VOTESS_F32) != f32)

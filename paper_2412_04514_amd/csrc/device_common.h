@@ -27,6 +27,48 @@ __device__ __forceinline__ double dist2_nc(double x, double y, double z) {
   return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
 }
 
+// Dense grid cells (more than kSubMin points) carry a sub-grid over a box
+// [lo, lo + e] that holds the central 90% of their points along each axis:
+// m0 x m1 x m2 sub-cells with m0 m1 m2 <= count / 2, near-cubic; points
+// inside such a cell are ordered by sub-cell id s0 + m0 (s1 + m1 s2),
+// s_a = clamp(floor((x_a - lo_a) ih_a), 0, m_a - 1), ih_a = m_a / e_a.
+// Its record in sub_start (16-byte aligned): m0, m1, m2, 0, lo[3] and ih[3]
+// as doubles, then the m0 m1 m2 + 1 sub-cell starts relative to the cell's
+// first point.
+constexpr int kSubMin = 16;
+#ifndef VOTESS_SUB_PTS
+#define VOTESS_SUB_PTS 2
+#endif
+constexpr int kSubPts = VOTESS_SUB_PTS;  // points per sub-cell the sub-grid aims at (>= 2)
+constexpr int kSubHead = 16;  // int32 words before the starts
+constexpr int kSubBins = 1024;  // histogram bins per axis for the sub-grid box
+__device__ __forceinline__ int sub_axis(double x, double lo, double ih, int m) {
+  double s = floor((x - lo) * ih);
+  s = fmin(fmax(s, 0.0), (double)(m - 1));  // NaN -> 0
+  return (int)s;
+}
+struct SubCell {
+  int m0, m1, m2;
+  double lo0, lo1, lo2, ih0, ih1, ih2;
+  const int* start;  // m0 m1 m2 + 1 starts
+};
+__device__ __forceinline__ SubCell sub_cell(const int* rec) {
+  SubCell c;
+  const int4 m = *(const int4*)rec;
+  c.m0 = m.x;
+  c.m1 = m.y;
+  c.m2 = m.z;
+  const double2 a = *(const double2*)(rec + 4), b = *(const double2*)(rec + 8), d = *(const double2*)(rec + 12);
+  c.lo0 = a.x;
+  c.lo1 = a.y;
+  c.lo2 = b.x;
+  c.ih0 = b.y;
+  c.ih1 = d.x;
+  c.ih2 = d.y;
+  c.start = rec + kSubHead;
+  return c;
+}
+
 template <typename T> struct Rec;
 template <> struct Rec<float> {
   using type = float4;

@@ -25,7 +25,6 @@ GridDev to_dev(const votess_grid& g) {
 
 namespace {
 
-constexpr int kSmallCell = 16;    // cells up to this size are reordered by one thread
 constexpr int kLdsSortMax = 4096; // larger cells sort their keys in global memory
 
 template <typename T>
@@ -55,13 +54,14 @@ __global__ void k_scatter(const T* __restrict__ pts, int n, const int2* __restri
 template <typename T>
 __global__ void k_order_small(const typename Rec<T>::type* __restrict__ tmp, const int* __restrict__ cell_start,
                               int ncells, typename Rec<T>::type* __restrict__ out, int* __restrict__ perm,
-                              int* __restrict__ big, int* __restrict__ nbig) {
+                              int* __restrict__ big, int* __restrict__ nbig, int2* __restrict__ subinfo) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   const int b = cell_start[c], e = cell_start[c + 1];
   const int len = e - b;
+  if (subinfo) subinfo[c] = make_int2(-1, 0);
   if (len == 0) return;
-  if (len > kSmallCell) {
+  if (len > kSubMin) {  // dense cell: sub-grid order, one block per cell
     big[atomicAdd(nbig, 1)] = c;
     return;
   }
@@ -78,52 +78,188 @@ __global__ void k_order_small(const typename Rec<T>::type* __restrict__ tmp, con
 // Bitonic sort (all comparators ascending: the first stage of each merge
 // compares mirrored pairs), over len keys; virtual padding to a power of two
 // is +inf, so comparisons with an index >= len are skipped.
-template <typename KeyPtr>
-__device__ void block_bitonic(KeyPtr key, int len) {
+// Keys are unique, so the payload (source position) follows its key.
+__device__ __forceinline__ void cswap(unsigned long long* key, unsigned* val, int t, int p) {
+  const unsigned long long a = key[t], b = key[p];
+  if (b < a) {
+    key[t] = b;
+    key[p] = a;
+    const unsigned va = val[t];
+    val[t] = val[p];
+    val[p] = va;
+  }
+}
+__device__ void block_bitonic(unsigned long long* key, unsigned* val, int len) {
   int P = 1;
   while (P < len) P <<= 1;
   for (int k = 2; k <= P; k <<= 1) {
     for (int t = threadIdx.x; t < len; t += blockDim.x) {
       const int p = t ^ (k - 1);
-      if (p > t && p < len) {
-        const unsigned long long a = key[t], b = key[p];
-        if (b < a) { key[t] = b; key[p] = a; }
-      }
+      if (p > t && p < len) cswap(key, val, t, p);
     }
     __syncthreads();
     for (int j = k >> 2; j >= 1; j >>= 1) {
       for (int t = threadIdx.x; t < len; t += blockDim.x) {
         const int p = t ^ j;
-        if (p > t && p < len) {
-          const unsigned long long a = key[t], b = key[p];
-          if (b < a) { key[t] = b; key[p] = a; }
-        }
+        if (p > t && p < len) cswap(key, val, t, p);
       }
       __syncthreads();
     }
   }
 }
 
+// Sub-grid of a dense cell from the extents of its box: near-cubic
+// sub-cells, m0 m1 m2 <= count / kSubPts (each m_a >= 1).
+__device__ void plan_sub(int count, double e0, double e1, double e2, int& m0, int& m1, int& m2) {
+  const double target = (double)(count / kSubPts);
+  const double s = cbrt(target / (e0 * e1 * e2));
+  m0 = (int)fmin(fmax(floor(e0 * s), 1.0), 4096.0);
+  m1 = (int)fmin(fmax(floor(e1 * s), 1.0), 4096.0);
+  m2 = (int)fmin(fmax(floor(e2 * s), 1.0), 4096.0);
+  while ((long long)m0 * m1 * m2 > count / kSubPts) {
+    if (m0 >= m1 && m0 >= m2) --m0;
+    else if (m1 >= m2) --m1;
+    else --m2;
+  }
+}
+
+// One block per dense cell: order its points by (sub-cell, original index)
+// and write its sub-grid record (see device_common.h).  The sub-grid spans,
+// per axis, the central 90% of the cell's points (from a histogram of
+// kSubBins bins over their bounding box); points beyond fall in the edge
+// sub-cells.
 template <typename T>
 __global__ __launch_bounds__(256) void k_order_big(const typename Rec<T>::type* __restrict__ tmp,
                                                    const int* __restrict__ cell_start, const int* __restrict__ big,
-                                                   const int* __restrict__ nbig, typename Rec<T>::type* __restrict__ out,
-                                                   int* __restrict__ perm, unsigned long long* __restrict__ gkey) {
+                                                   const int* __restrict__ nbig, GridDev G,
+                                                   typename Rec<T>::type* __restrict__ out, int* __restrict__ perm,
+                                                   unsigned long long* __restrict__ gkey, unsigned* __restrict__ gval,
+                                                   int2* __restrict__ subinfo, int* __restrict__ sub_start,
+                                                   int* __restrict__ sub_total) {
   __shared__ unsigned long long skey[kLdsSortMax];
+  __shared__ unsigned sval[kLdsSortMax];
+  __shared__ double sbox[4][6];
+  __shared__ int shist[3][kSubBins];
+  __shared__ int soff, sm[3];
+  __shared__ double slo[3], sih[3];
   const int nb = *nbig;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int q = blockIdx.x; q < nb; q += gridDim.x) {
     const int c = big[q];
     const int b = cell_start[c], len = cell_start[c + 1] - b;
     const bool lds = len <= kLdsSortMax;
     unsigned long long* key = lds ? skey : gkey + b;
-    for (int t = threadIdx.x; t < len; t += blockDim.x)
-      key[t] = ((unsigned long long)(unsigned)Rec<T>::id(tmp[b + t]) << 32) | (unsigned)t;
-    __syncthreads();
-    block_bitonic(key, len);
+    unsigned* val = lds ? sval : gval + b;
+    if (subinfo) {
+      // bounding box of the cell's points
+      double mn0 = 1e300, mn1 = 1e300, mn2 = 1e300, mx0 = -1e300, mx1 = -1e300, mx2 = -1e300;
+      for (int t = threadIdx.x; t < len; t += blockDim.x) {
+        const auto r = tmp[b + t];
+        mn0 = fmin(mn0, (double)r.x); mx0 = fmax(mx0, (double)r.x);
+        mn1 = fmin(mn1, (double)r.y); mx1 = fmax(mx1, (double)r.y);
+        mn2 = fmin(mn2, (double)r.z); mx2 = fmax(mx2, (double)r.z);
+      }
+      for (int o = 32; o >= 1; o >>= 1) {
+        mn0 = fmin(mn0, __shfl_xor(mn0, o, 64)); mx0 = fmax(mx0, __shfl_xor(mx0, o, 64));
+        mn1 = fmin(mn1, __shfl_xor(mn1, o, 64)); mx1 = fmax(mx1, __shfl_xor(mx1, o, 64));
+        mn2 = fmin(mn2, __shfl_xor(mn2, o, 64)); mx2 = fmax(mx2, __shfl_xor(mx2, o, 64));
+      }
+      if (lane == 0) {
+        sbox[wid][0] = mn0; sbox[wid][1] = mn1; sbox[wid][2] = mn2;
+        sbox[wid][3] = mx0; sbox[wid][4] = mx1; sbox[wid][5] = mx2;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int nw = (int)(blockDim.x + 63) >> 6;
+        for (int w = 1; w < nw; ++w) {
+          mn0 = fmin(mn0, sbox[w][0]); mn1 = fmin(mn1, sbox[w][1]); mn2 = fmin(mn2, sbox[w][2]);
+          mx0 = fmax(mx0, sbox[w][3]); mx1 = fmax(mx1, sbox[w][4]); mx2 = fmax(mx2, sbox[w][5]);
+        }
+        sbox[0][0] = mn0; sbox[0][1] = mn1; sbox[0][2] = mn2;
+        sbox[0][3] = mx0; sbox[0][4] = mx1; sbox[0][5] = mx2;
+      }
+      for (int t = threadIdx.x; t < 3 * kSubBins; t += blockDim.x) (&shist[0][0])[t] = 0;
+      __syncthreads();
+      // per-axis histograms over the bounding box
+      for (int t = threadIdx.x; t < len; t += blockDim.x) {
+        const auto r = tmp[b + t];
+        const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double lo = sbox[0][a], w = sbox[0][3 + a] - lo;
+          const int bin = w > 0.0 ? (int)fmin((x[a] - lo) / w * kSubBins, (double)(kSubBins - 1)) : 0;
+          atomicAdd(&shist[a][bin], 1);
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x < 3) {
+        // the box of the central 90% of the points along this axis
+        const int a = threadIdx.x;
+        const double lo = sbox[0][a], w = sbox[0][3 + a] - lo;
+        const int cut_lo = len / 20, cut_hi = len - len / 20;
+        int acc = 0, blo = 0, bhi = kSubBins - 1;
+        bool got_lo = false;
+        for (int i = 0; i < kSubBins; ++i) {
+          const int next = acc + shist[a][i];
+          if (!got_lo && next > cut_lo) { blo = i; got_lo = true; }
+          if (next >= cut_hi) { bhi = i; break; }
+          acc = next;
+        }
+        slo[a] = lo + w * ((double)blo / kSubBins);
+        sih[a] = fmax(w * ((double)(bhi + 1 - blo) / kSubBins), (a == 0 ? G.h0 : a == 1 ? G.h1 : G.h2) * 0x1p-30);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        // sih holds the extents here
+        const double e0 = sih[0], e1 = sih[1], e2 = sih[2];
+        int m0, m1, m2;
+        plan_sub(len, e0, e1, e2, m0, m1, m2);
+        sm[0] = m0; sm[1] = m1; sm[2] = m2;
+        sih[0] = m0 / e0; sih[1] = m1 / e1; sih[2] = m2 / e2;
+        const int words = (kSubHead + m0 * m1 * m2 + 1 + 3) & ~3;
+        soff = atomicAdd(sub_total, words);
+      }
+      __syncthreads();
+    }
+    const int m0 = subinfo ? sm[0] : 1, m1 = subinfo ? sm[1] : 1, m2 = subinfo ? sm[2] : 1;
+    const double lo0 = subinfo ? slo[0] : 0.0, lo1 = subinfo ? slo[1] : 0.0, lo2 = subinfo ? slo[2] : 0.0;
+    const double ih0 = subinfo ? sih[0] : 0.0, ih1 = subinfo ? sih[1] : 0.0, ih2 = subinfo ? sih[2] : 0.0;
     for (int t = threadIdx.x; t < len; t += blockDim.x) {
-      const unsigned long long kv = key[t];
-      out[b + t] = tmp[b + (int)(kv & 0xffffffffu)];
-      perm[b + t] = (int)(kv >> 32);
+      const auto r = tmp[b + t];
+      unsigned sid = 0;
+      if (subinfo)
+        sid = (unsigned)(sub_axis(r.x, lo0, ih0, m0) + m0 * (sub_axis(r.y, lo1, ih1, m1) + m1 * sub_axis(r.z, lo2, ih2, m2)));
+      key[t] = ((unsigned long long)sid << 32) | (unsigned)Rec<T>::id(r);
+      val[t] = (unsigned)t;
+    }
+    __syncthreads();
+    block_bitonic(key, val, len);
+    for (int t = threadIdx.x; t < len; t += blockDim.x) {
+      out[b + t] = tmp[b + (int)val[t]];
+      perm[b + t] = (int)(unsigned)(key[t] & 0xffffffffu);
+    }
+    if (subinfo) {
+      const int off = soff;
+      const int ns = m0 * m1 * m2;
+      int* rec = sub_start + off;
+      if (threadIdx.x == 0) {
+        *(int4*)rec = make_int4(m0, m1, m2, 0);
+        *(double2*)(rec + 4) = make_double2(lo0, lo1);
+        *(double2*)(rec + 8) = make_double2(lo2, ih0);
+        *(double2*)(rec + 12) = make_double2(ih1, ih2);
+        subinfo[c] = make_int2(off, ns);
+      }
+      for (int sc = threadIdx.x; sc <= ns; sc += blockDim.x) {
+        // first position whose sub-cell id is >= sc
+        int lo = 0, hi = len;
+        const unsigned long long want = (unsigned long long)sc << 32;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (key[mid] < want) lo = mid + 1;
+          else hi = mid;
+        }
+        rec[kSubHead + sc] = lo;
+      }
     }
     __syncthreads();
   }
@@ -235,15 +371,19 @@ votess_status scan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, Worksp
 }
 
 size_t grid_sort_workspace(int64_t n, int64_t ncells) {
-  // cell/rank pairs, counts, unordered records (<= 32 B), big-cell list,
-  // global sort keys, scan scratch
+  // cell/rank pairs, counts, unordered records (<= 32 B), dense-cell list,
+  // global sort keys and payloads, scan scratch
   return Workspace::align(n * 8) + Workspace::align(ncells * 4 + 4) + Workspace::align(n * 32) +
-         Workspace::align(ncells * 4 + 64) + Workspace::align(n * 8) + scan_workspace(ncells) + 4096;
+         Workspace::align(ncells * 4 + 64) + Workspace::align(n * 8) + Workspace::align(n * 4) +
+         scan_workspace(ncells) + 4096;
 }
 
+// dense cells hold > 16 points each: sum of (16 + count / 2 + 1 + 3) <= n / 2 + 20 n / 17
+int64_t sub_capacity(int64_t n) { return n / 2 + (20 * n) / 17 + 1024; }
+
 votess_status launch_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dt, int n, const GridDev& G,
-                               int64_t ncells, int32_t* cell_start, int32_t* perm, void* sorted, Workspace& ws,
-                               hipStream_t st) {
+                               int64_t ncells, int32_t* cell_start, int32_t* perm, void* sorted, int32_t* subinfo,
+                               int32_t* sub_start, Workspace& ws, hipStream_t st) {
   const size_t mark = ws.used;
   int2* cr = ws.take<int2>(n > 0 ? n : 1);
   int* count = ws.take<int>(ncells + 1);
@@ -251,8 +391,10 @@ votess_status launch_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dt
   int* big = ws.take<int>(ncells + 16);
   int* nbig = ctx->d_counter;
   unsigned long long* gkey = ws.take<unsigned long long>(n > 0 ? n : 1);
+  unsigned* gval = ws.take<unsigned>(n > 0 ? n : 1);
+  int* sub_total = ctx->d_counter + 1;
   VT_HIP(hipMemsetAsync(count, 0, (ncells + 1) * sizeof(int), st));
-  VT_HIP(hipMemsetAsync(nbig, 0, sizeof(int), st));
+  VT_HIP(hipMemsetAsync(nbig, 0, 2 * sizeof(int), st));
   const int TB = 256;
   const unsigned nblk = (unsigned)((n + TB - 1) / TB);
   if (n > 0) {
@@ -268,14 +410,15 @@ votess_status launch_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dt
     if (dt == VOTESS_F32) {
       k_scatter<float><<<nblk, TB, 0, st>>>((const float*)pts, n, cr, cell_start, (float4*)tmp);
       k_order_small<float><<<cblk, TB, 0, st>>>((const float4*)tmp, cell_start, (int)ncells, (float4*)sorted, perm,
-                                                big, nbig);
-      k_order_big<float><<<512, 256, 0, st>>>((const float4*)tmp, cell_start, big, nbig, (float4*)sorted, perm, gkey);
+                                                big, nbig, (int2*)subinfo);
+      k_order_big<float><<<512, 256, 0, st>>>((const float4*)tmp, cell_start, big, nbig, G, (float4*)sorted, perm,
+                                              gkey, gval, (int2*)subinfo, sub_start, sub_total);
     } else {
       k_scatter<double><<<nblk, TB, 0, st>>>((const double*)pts, n, cr, cell_start, (double4*)tmp);
       k_order_small<double><<<cblk, TB, 0, st>>>((const double4*)tmp, cell_start, (int)ncells, (double4*)sorted,
-                                                 perm, big, nbig);
-      k_order_big<double><<<512, 256, 0, st>>>((const double4*)tmp, cell_start, big, nbig, (double4*)sorted, perm,
-                                               gkey);
+                                                 perm, big, nbig, (int2*)subinfo);
+      k_order_big<double><<<512, 256, 0, st>>>((const double4*)tmp, cell_start, big, nbig, G, (double4*)sorted, perm,
+                                               gkey, gval, (int2*)subinfo, sub_start, sub_total);
     }
     VT_HIP(hipGetLastError());
   }

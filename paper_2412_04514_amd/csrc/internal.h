@@ -16,6 +16,8 @@ namespace votess {
 
 // ------------------------------------------------------------------ errors
 votess_status fail(votess_status s, const char* fmt, ...);
+// Sub-grid buffers of votess_grid_sort: both or neither, 16-byte aligned.
+votess_status check_sub(const int32_t* subinfo, const int32_t* sub_start, int64_t n, const char* where);
 #define VT_HIP(call)                                                                 \
   do {                                                                               \
     hipError_t e_ = (call);                                                          \
@@ -79,8 +81,17 @@ void dev_free(votess_ctx* ctx, void* p);
 // grid sort (grid_sort.hip)
 size_t grid_sort_workspace(int64_t n, int64_t ncells);
 votess_status launch_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dt, int n, const GridDev& G,
-                               int64_t ncells, int32_t* cell_start, int32_t* perm, void* sorted, Workspace& ws,
-                               hipStream_t st);
+                               int64_t ncells, int32_t* cell_start, int32_t* perm, void* sorted, int32_t* subinfo,
+                               int32_t* sub_start, Workspace& ws, hipStream_t st);
+int64_t sub_capacity(int64_t n);
+
+// Sub-grids of dense cells: subinfo[2 c] = offset into sub_start (or -1),
+// subinfo[2 c + 1] = m; sub_start[offset + s] = first point of sub-cell s
+// relative to cell_start[c], for s = 0..m^3.
+struct SubGrid {
+  const int2* info = nullptr;
+  const int* start = nullptr;
+};
 
 // exclusive scan: out[0..n] with out[n] = total (grid_sort.hip)
 size_t scan_workspace(int64_t n);
@@ -89,8 +100,8 @@ votess_status scan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, Worksp
 
 // k-NN (knn.hip)
 votess_status launch_knn(votess_ctx* ctx, const void* sorted, votess_dtype dt, int n, const GridDev& G,
-                         const int32_t* cell_start, const int32_t* queries, int nq, int k, votess_dtype dist,
-                         int32_t* knn, hipStream_t st);
+                         const int32_t* cell_start, const SubGrid& sub, const int32_t* queries, int nq, int k,
+                         votess_dtype dist, int32_t* knn, hipStream_t st);
 
 // clipping (clip.hip)
 struct ClipLaunch {
@@ -118,6 +129,7 @@ struct ClipLaunch {
   int stream = 0;                // 1: uncertified cells continue by grid rings
   const int32_t* cell_start = nullptr;
   GridDev grid{};
+  SubGrid sub{};
 };
 votess_status launch_clip(const ClipLaunch& a, hipStream_t st);
 

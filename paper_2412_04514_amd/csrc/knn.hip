@@ -1,91 +1,101 @@
 // k-nearest-neighbour search over the grid (paper, Summary: after the grid
 // sort "a k-nearest neighbors search is performed").
 //
-// One query per lane, queries in grid-sorted order so that neighbouring lanes
-// scan overlapping grid cells (L1/L2 reuse).  Each lane walks Chebyshev rings
-// r = 0, 1, 2, ... of grid cells around its own cell; a full x-row of a ring is
-// one contiguous range of sorted points.  The k best candidates live in VGPRs
-// as an ascending list updated by an unrolled compare-swap pass (no dynamic
-// register indexing), entered only when a candidate beats the current k-th.
-// The search stops after ring r once the list is full and its k-th distance
-// is below rho_r, the distance from the query to the nearest face of the
-// scanned block (faces on the grid boundary are at infinity).
+// A group of G lanes serves one query (queries in grid-sorted order, so that
+// neighbouring groups scan overlapping grid cells), in two phases:
+//   A. a seed block around the query -- sub-cells of its own dense cell, or
+//      grid cells -- grown ring by ring until the cell / sub-cell starts show
+//      at least K other points in it, then scanned whole: the list is full;
+//   B. every other grid-cell row, and sub-cell row of a dense cell, that
+//      meets the ball of the list's current k-th distance, each row cut to
+//      the ball (which shrinks as the list improves): one contiguous range of
+//      sorted points per row, split at dense cells.
+// The control flow is the same in every lane of the group; the candidates of
+// a range are taken G at a time (one coalesced load), and each that beats the
+// current k-th is inserted by rank into the ascending list, which the group
+// holds as E = K / G consecutive entries per lane.
 #include "internal.h"
 #include "device_common.h"
 
 #include <cfloat>
+#include <climits>
 
 namespace votess {
 namespace {
 
-// Ascending (d^2, sorted index) list.  FP32 distances pack into one u64 key:
-// the bits of a non-negative float order like the float.
-template <int K>
-struct ListF32 {
-  unsigned long long key[K];
-  __device__ void init() {
-#pragma unroll
-    for (int i = 0; i < K; ++i) key[i] = ~0ull;
-  }
-  __device__ bool better(float d2, int idx) const {
-    const unsigned long long x = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)idx;
-    return x < key[K - 1];
-  }
-  __device__ void insert(float d2, int idx) {
-    unsigned long long x = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)idx;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const unsigned long long a = key[i];
-      const bool lt = x < a;
-      key[i] = lt ? x : a;
-      x = lt ? a : x;
-    }
-  }
-  __device__ double worst() const { return (double)__uint_as_float((unsigned)(key[K - 1] >> 32)); }
-  __device__ bool full() const { return key[K - 1] != ~0ull; }
-  __device__ int idx(int i) const { return key[i] == ~0ull ? -1 : (int)(unsigned)(key[i] & 0xffffffffu); }
-  __device__ double d2(int i) const { return (double)__uint_as_float((unsigned)(key[i] >> 32)); }
+// List keys ordered by (d^2, sorted index).  FP32 distances pack into one
+// u64: the bits of a non-negative float order like the float.
+template <typename D>
+struct KeyOps;
+template <>
+struct KeyOps<float> {
+  using Key = unsigned long long;
+  __device__ static Key make(float d2, int j) { return ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)j; }
+  __device__ static Key inf() { return ~0ull; }
+  __device__ static bool less(Key a, Key b) { return a < b; }
+  __device__ static bool finite(Key a) { return a != ~0ull; }
+  __device__ static double d2(Key a) { return (double)__uint_as_float((unsigned)(a >> 32)); }
+  __device__ static int idx(Key a) { return a == ~0ull ? -1 : (int)(unsigned)(a & 0xffffffffu); }
+  __device__ static Key shfl(Key a, int src) { return __shfl(a, src, 64); }
+};
+template <>
+struct KeyOps<double> {
+  struct Key {
+    double d;
+    int i;
+  };
+  __device__ static Key make(double d2, int j) { return {d2, j}; }
+  __device__ static Key inf() { return {DBL_MAX, INT_MAX}; }
+  __device__ static bool less(const Key& a, const Key& b) { return a.d < b.d || (a.d == b.d && a.i < b.i); }
+  __device__ static bool finite(const Key& a) { return a.i != INT_MAX; }
+  __device__ static double d2(const Key& a) { return a.d; }
+  __device__ static int idx(const Key& a) { return a.i == INT_MAX ? -1 : a.i; }
+  __device__ static Key shfl(const Key& a, int src) { return {__shfl(a.d, src, 64), __shfl(a.i, src, 64)}; }
 };
 
-template <int K>
-struct ListF64 {
-  double d[K];
-  int id[K];
+// Ascending list of K keys over a group of G lanes: lane l holds ranks
+// l E .. l E + E - 1.  Every call is made by all G lanes of the group.
+template <typename D, int G, int E>
+struct GroupList {
+  using O = KeyOps<D>;
+  using Key = typename O::Key;
+  Key key[E];
   __device__ void init() {
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      d[i] = DBL_MAX;
-      id[i] = 0x7fffffff;
-    }
+    for (int e = 0; e < E; ++e) key[e] = O::inf();
   }
-  __device__ bool better(double x, int idx) const {
-    return x < d[K - 1] || (x == d[K - 1] && idx < id[K - 1]);
-  }
-  __device__ void insert(double x, int idx) {
+  __device__ Key worst(int gb) const { return O::shfl(key[E - 1], gb + G - 1); }
+  // insert x (the same in every lane): its rank is the number of smaller
+  // keys; ranks above it move up by one, the old k-th falls off
+  __device__ void insert(const Key& x, int lane, int l) {
+    int c = 0;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const double a = d[i];
-      const int b = id[i];
-      const bool lt = x < a || (x == a && idx < b);
-      d[i] = lt ? x : a;
-      id[i] = lt ? idx : b;
-      x = lt ? a : x;
-      idx = lt ? b : idx;
+    for (int e = 0; e < E; ++e) c += O::less(key[e], x) ? 1 : 0;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) c += __shfl_xor(c, o, 64);
+    const Key prev = O::shfl(key[E - 1], lane > 0 ? lane - 1 : 0);
+#pragma unroll
+    for (int e = E - 1; e >= 0; --e) {
+      const int p = l * E + e;
+      const Key below = e > 0 ? key[e > 0 ? e - 1 : 0] : prev;
+      key[e] = p < c ? key[e] : (p == c ? x : below);
     }
   }
-  __device__ double worst() const { return d[K - 1]; }
-  __device__ bool full() const { return id[K - 1] != 0x7fffffff; }
-  __device__ int idx(int i) const { return id[i] == 0x7fffffff ? -1 : id[i]; }
-  __device__ double d2(int i) const { return d[i]; }
 };
 
-template <typename T, typename D, int K>
-__global__ __launch_bounds__(64) void k_knn(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
-                                            const int* __restrict__ cell_start, const int* __restrict__ queries,
-                                            int nq, int* __restrict__ knn, unsigned* __restrict__ err) {
-  using List = typename std::conditional<std::is_same<D, float>::value, ListF32<K>, ListF64<K>>::type;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+template <typename T, typename D, int K, int GS>
+__global__ __launch_bounds__(256) void k_knn(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
+                                             const int* __restrict__ cell_start, SubGrid sub,
+                                             const int* __restrict__ queries, int nq, int* __restrict__ knn,
+                                             unsigned* __restrict__ err) {
+  constexpr int E = K / GS;
+  static_assert(E * GS == K, "K must be a multiple of GS");
+  using O = KeyOps<D>;
+  using Key = typename O::Key;
+  const int lane = threadIdx.x & 63;
+  const int l = lane & (GS - 1), gb = lane - l;
+  const int q = (int)((blockIdx.x * blockDim.x + threadIdx.x) / GS);
+  if (q >= nq) return;  // whole groups leave together
   const int s = queries ? queries[q] : q;
   const auto pr = rec[s];
   const D px = (D)pr.x, py = (D)pr.y, pz = (D)pr.z;
@@ -93,77 +103,198 @@ __global__ __launch_bounds__(64) void k_knn(const typename Rec<T>::type* __restr
   const int cy = axis_cell((double)pr.y, G.lo1, G.ih1, G.g1);
   const int cz = axis_cell((double)pr.z, G.lo2, G.ih2, G.g2);
   const double ext = fmax(G.hi0 - G.lo0, fmax(G.hi1 - G.lo1, G.hi2 - G.lo2));
-  const double margin = 1e-9 * ext;  // covers floor() rounding at grid-cell borders
-  // a float d^2 may be low by a few ulp: stop only below rho^2 (1 - 1e-6)
-  const double stop_scale = std::is_same<D, float>::value ? (1.0 - 1e-6) : 1.0;
+  const double margin = 1e-9 * ext;  // covers floor() rounding at cell borders
 
-  List L;
+  GroupList<D, GS, E> L;
   L.init();
-  auto scan = [&](int b, int e) {
-    for (int j = b; j < e; ++j) {
-      if (j == s) continue;
-      const auto qr = rec[j];
-      const D dx = (D)qr.x - px, dy = (D)qr.y - py, dz = (D)qr.z - pz;
-      const D d2 = dist2_nc(dx, dy, dz);
-      if (L.better(d2, j)) L.insert(d2, j);
+  Key wk = O::inf();  // the list's k-th key (group-uniform)
+  const double p0 = (double)pr.x, p1 = (double)pr.y, p2 = (double)pr.z;
+  const unsigned long long gmask = (GS == 64) ? ~0ull : ((1ull << GS) - 1ull);
+
+  // candidates [jb, je), GS at a time; each that beats the k-th is inserted
+  auto scan = [&](int jb, int je) {
+    for (int base = jb; base < je; base += GS) {
+      const int j = base + l;
+      Key ck = O::inf();
+      if (j < je && j != s) {
+        const auto qr = rec[j];
+        ck = O::make(dist2_nc((D)qr.x - px, (D)qr.y - py, (D)qr.z - pz), j);
+      }
+      bool pass = O::less(ck, wk);
+      unsigned long long m = (__ballot(pass) >> gb) & gmask;
+      while (m) {
+        const int b = __ffsll((long long)m) - 1;
+        const Key x = O::shfl(ck, gb + b);
+        L.insert(x, lane, l);
+        wk = L.worst(gb);
+        pass = pass && l != b && O::less(ck, wk);
+        m = (__ballot(pass) >> gb) & gmask;
+      }
     }
   };
-  for (int r = 0;; ++r) {
-    const int z0 = max(cz - r, 0), z1 = min(cz + r, G.g2 - 1);
-    const int y0 = max(cy - r, 0), y1 = min(cy + r, G.g1 - 1);
-    const int x0 = max(cx - r, 0), x1 = min(cx + r, G.g0 - 1);
-    for (int z = z0; z <= z1; ++z) {
-      const bool zface = (z == cz - r) || (z == cz + r);
-      for (int y = y0; y <= y1; ++y) {
+  // squared search radius: the k-th distance with slack for float rounding
+  // of d^2 (the list is full whenever it is used)
+  auto rad2 = [&]() { return O::d2(wk) * (1.0 + 1e-6); };
+  // distance from p to [a, b], less the rounding margin
+  auto gap = [&](double p, double a_, double b_) { return fmax(0.0, fmax(a_ - p, p - b_) - margin); };
+
+  // ---- phase A: a seed block around the query that holds at least K other
+  // points (counted from the cell and sub-cell starts), scanned whole; it
+  // fills the list, and its k-th distance bounds the search
+  const int c0 = cx + G.g0 * (cy + G.g1 * cz);
+  const int2 info0 = sub.info ? sub.info[c0] : make_int2(-1, 0);
+  const bool seed_sub = info0.x >= 0 && cell_start[c0 + 1] - cell_start[c0] >= K + 1;
+  int bx0, bx1, by0, by1, bz0, bz1;  // the seed block: sub-cells of the own cell, or grid cells
+  if (seed_sub) {
+    const int* srec = sub.start + info0.x;
+    const SubCell sc = sub_cell(srec);
+    const int base0 = cell_start[c0];
+    const int qx = sub_axis(p0, sc.lo0, sc.ih0, sc.m0), qy = sub_axis(p1, sc.lo1, sc.ih1, sc.m1),
+              qz = sub_axis(p2, sc.lo2, sc.ih2, sc.m2);
+    for (int rs = 0;; ++rs) {
+      bx0 = max(qx - rs, 0); bx1 = min(qx + rs, sc.m0 - 1);
+      by0 = max(qy - rs, 0); by1 = min(qy + rs, sc.m1 - 1);
+      bz0 = max(qz - rs, 0); bz1 = min(qz + rs, sc.m2 - 1);
+      int cnt = 0;
+      for (int z = bz0; z <= bz1; ++z)
+        for (int y = by0; y <= by1; ++y) {
+          const int row = kSubHead + sc.m0 * (y + sc.m1 * z);
+          cnt += srec[row + bx1 + 1] - srec[row + bx0];
+        }
+      if (cnt >= K + 1 || (bx0 == 0 && by0 == 0 && bz0 == 0 && bx1 == sc.m0 - 1 && by1 == sc.m1 - 1 &&
+                           bz1 == sc.m2 - 1))
+        break;
+    }
+    for (int z = bz0; z <= bz1; ++z)
+      for (int y = by0; y <= by1; ++y) {
+        const int row = kSubHead + sc.m0 * (y + sc.m1 * z);
+        scan(base0 + srec[row + bx0], base0 + srec[row + bx1 + 1]);
+      }
+  } else {
+    for (int r = 0;; ++r) {
+      bx0 = max(cx - r, 0); bx1 = min(cx + r, G.g0 - 1);
+      by0 = max(cy - r, 0); by1 = min(cy + r, G.g1 - 1);
+      bz0 = max(cz - r, 0); bz1 = min(cz + r, G.g2 - 1);
+      int cnt = 0;
+      for (int z = bz0; z <= bz1; ++z)
+        for (int y = by0; y <= by1; ++y) {
+          const int row = G.g0 * (y + G.g1 * z);
+          cnt += cell_start[row + bx1 + 1] - cell_start[row + bx0];
+        }
+      if (cnt >= K + 1 || (bx0 == 0 && by0 == 0 && bz0 == 0 && bx1 == G.g0 - 1 && by1 == G.g1 - 1 &&
+                           bz1 == G.g2 - 1))
+        break;
+    }
+    for (int z = bz0; z <= bz1; ++z)
+      for (int y = by0; y <= by1; ++y) {
         const int row = G.g0 * (y + G.g1 * z);
-        if (zface || y == cy - r || y == cy + r) {
-          scan(cell_start[row + x0], cell_start[row + x1 + 1]);
-        } else {
-          if (cx - r >= 0) scan(cell_start[row + cx - r], cell_start[row + cx - r + 1]);
-          if (r > 0 && cx + r < G.g0) scan(cell_start[row + cx + r], cell_start[row + cx + r + 1]);
+        scan(cell_start[row + bx0], cell_start[row + bx1 + 1]);
+      }
+  }
+
+  // ---- phase B: every other grid cell / sub-cell row that meets the ball of
+  // the list's k-th distance (re-cut to the shrinking ball row by row)
+  // a dense cell c (grid coordinates ccx, ccy, ccz), without the seed block
+  // when it is the query's own cell
+  auto scan_dense = [&](int c, int ccx, int ccy, int ccz, bool own) {
+    const int* drec = sub.start + sub.info[c].x;
+    const SubCell sc = sub_cell(drec);
+    const int base = cell_start[c];
+    const double w1 = 1.0 / sc.ih1, w2 = 1.0 / sc.ih2;
+    const double ylo = G.lo1 + ccy * G.h1, yhi = ylo + G.h1, zlo = G.lo2 + ccz * G.h2, zhi = zlo + G.h2;
+    const double rz = sqrt(rad2()) + margin;
+    const int sz0 = sub_axis(p2 - rz, sc.lo2, sc.ih2, sc.m2), sz1 = sub_axis(p2 + rz, sc.lo2, sc.ih2, sc.m2);
+    for (int sz = sz0; sz <= sz1; ++sz) {
+      // edge sub-cells reach the cell's faces (points beyond the sub-grid box)
+      const double za = sz == 0 ? zlo : sc.lo2 + sz * w2, zb = sz == sc.m2 - 1 ? zhi : sc.lo2 + (sz + 1) * w2;
+      const double gz = gap(p2, za, zb);
+      const double remz = rad2() - gz * gz;
+      if (remz < 0.0) continue;
+      const double ry = sqrt(remz) + margin;
+      const int sy0 = sub_axis(p1 - ry, sc.lo1, sc.ih1, sc.m1), sy1 = sub_axis(p1 + ry, sc.lo1, sc.ih1, sc.m1);
+      for (int sy = sy0; sy <= sy1; ++sy) {
+        const double ya = sy == 0 ? ylo : sc.lo1 + sy * w1, yb = sy == sc.m1 - 1 ? yhi : sc.lo1 + (sy + 1) * w1;
+        const double gy = gap(p1, ya, yb);
+        const double rem = rad2() - gz * gz - gy * gy;
+        if (rem < 0.0) continue;
+        const double rx = sqrt(rem) + margin;
+        int sx0 = sub_axis(p0 - rx, sc.lo0, sc.ih0, sc.m0), sx1 = sub_axis(p0 + rx, sc.lo0, sc.ih0, sc.m0);
+        const int row = kSubHead + sc.m0 * (sy + sc.m1 * sz);
+        if (own && sy >= by0 && sy <= by1 && sz >= bz0 && sz <= bz1) {
+          if (sx0 < bx0) scan(base + drec[row + sx0], base + drec[row + min(sx1, bx0 - 1) + 1]);
+          sx0 = max(sx0, bx1 + 1);
+        }
+        if (sx0 <= sx1) scan(base + drec[row + sx0], base + drec[row + sx1 + 1]);
+      }
+    }
+  };
+  if (O::finite(wk)) {
+    const double rz = sqrt(rad2()) + margin;
+    const int gz0 = axis_cell(p2 - rz, G.lo2, G.ih2, G.g2), gz1 = axis_cell(p2 + rz, G.lo2, G.ih2, G.g2);
+    for (int z = gz0; z <= gz1; ++z) {
+      const double gz = gap(p2, G.lo2 + z * G.h2, G.lo2 + (z + 1) * G.h2);
+      const double remz = rad2() - gz * gz;
+      if (remz < 0.0) continue;
+      const double ry = sqrt(remz) + margin;
+      const int gy0 = axis_cell(p1 - ry, G.lo1, G.ih1, G.g1), gy1 = axis_cell(p1 + ry, G.lo1, G.ih1, G.g1);
+      for (int y = gy0; y <= gy1; ++y) {
+        const double gy = gap(p1, G.lo1 + y * G.h1, G.lo1 + (y + 1) * G.h1);
+        const double rem = rad2() - gz * gz - gy * gy;
+        if (rem < 0.0) continue;
+        const double rx = sqrt(rem) + margin;
+        const int x0 = axis_cell(p0 - rx, G.lo0, G.ih0, G.g0), x1 = axis_cell(p0 + rx, G.lo0, G.ih0, G.g0);
+        const int row = G.g0 * (y + G.g1 * z);
+        // grid cells of the seed block were scanned whole
+        const bool in_seed = !seed_sub && y >= by0 && y <= by1 && z >= bz0 && z <= bz1;
+        int x = x0;
+        while (x <= x1) {
+          if (in_seed && x >= bx0 && x <= bx1) {
+            x = bx1 + 1;
+            continue;
+          }
+          const int lim = (in_seed && x < bx0) ? min(x1, bx0 - 1) : x1;
+          int xe = x;
+          if (sub.info) {
+            while (xe <= lim && sub.info[row + xe].x < 0) ++xe;
+          } else {
+            xe = lim + 1;
+          }
+          if (xe > x) {  // a stretch of cells without sub-grids
+            scan(cell_start[row + x], cell_start[row + xe]);
+            x = xe;
+            continue;
+          }
+          scan_dense(row + x, x, y, z, seed_sub && row + x == c0);
+          ++x;
         }
       }
     }
-    const bool covers = cx - r <= 0 && cy - r <= 0 && cz - r <= 0 && cx + r >= G.g0 - 1 && cy + r >= G.g1 - 1 &&
-                        cz + r >= G.g2 - 1;
-    if (covers) break;
-    if (L.full()) {
-      double rho = 1e300;
-      const double p0 = (double)pr.x, p1 = (double)pr.y, p2 = (double)pr.z;
-      if (cx - r > 0) rho = fmin(rho, p0 - (G.lo0 + (cx - r) * G.h0));
-      if (cx + r + 1 < G.g0) rho = fmin(rho, (G.lo0 + (cx + r + 1) * G.h0) - p0);
-      if (cy - r > 0) rho = fmin(rho, p1 - (G.lo1 + (cy - r) * G.h1));
-      if (cy + r + 1 < G.g1) rho = fmin(rho, (G.lo1 + (cy + r + 1) * G.h1) - p1);
-      if (cz - r > 0) rho = fmin(rho, p2 - (G.lo2 + (cz - r) * G.h2));
-      if (cz + r + 1 < G.g2) rho = fmin(rho, (G.lo2 + (cz + r + 1) * G.h2) - p2);
-      rho -= margin;
-      if (rho > 0.0 && L.worst() < rho * rho * stop_scale) break;
-    }
   }
-  int* out = knn + (size_t)q * K;
+  int* out = knn + (size_t)q * K + l * E;
 #pragma unroll
-  for (int i = 0; i < K; ++i) out[i] = L.idx(i);
-  if (L.idx(0) >= 0 && L.d2(0) == 0.0) atomicOr(err, ERR_DUPLICATE);
+  for (int e = 0; e < E; ++e) out[e] = O::idx(L.key[e]);
+  if (l == 0 && O::finite(L.key[0]) && O::d2(L.key[0]) == 0.0) atomicOr(err, ERR_DUPLICATE);
 }
 
 template <typename T, typename D>
-votess_status dispatch_k(int k, const void* sorted, int n, const GridDev& G, const int32_t* cs, const int32_t* qs,
-                         int nq, int32_t* knn, unsigned* err, hipStream_t st) {
+votess_status dispatch_k(int k, const void* sorted, int n, const GridDev& G, const int32_t* cs, const SubGrid& sub,
+                         const int32_t* qs, int nq, int32_t* knn, unsigned* err, hipStream_t st) {
   using R4 = typename Rec<T>::type;
   const R4* rec = (const R4*)sorted;
-  const unsigned blocks = (unsigned)((nq + 63) / 64);
-#define VT_KNN_CASE(KK)                                                           \
-  case KK:                                                                        \
-    k_knn<T, D, KK><<<blocks, 64, 0, st>>>(rec, n, G, cs, qs, nq, knn, err);     \
-    break;
+#define VT_KNN_CASE(KK, GG)                                                                 \
+  case KK: {                                                                                \
+    const unsigned blocks = (unsigned)(((long long)nq * GG + 255) / 256);                   \
+    k_knn<T, D, KK, GG><<<blocks, 256, 0, st>>>(rec, n, G, cs, sub, qs, nq, knn, err);      \
+    break;                                                                                  \
+  }
   switch (k) {
-    VT_KNN_CASE(8)
-    VT_KNN_CASE(12)
-    VT_KNN_CASE(16)
-    VT_KNN_CASE(24)
-    VT_KNN_CASE(32)
-    VT_KNN_CASE(48)
-    VT_KNN_CASE(64)
+    VT_KNN_CASE(8, 4)
+    VT_KNN_CASE(12, 4)
+    VT_KNN_CASE(16, 4)
+    VT_KNN_CASE(24, 8)
+    VT_KNN_CASE(32, 8)
+    VT_KNN_CASE(48, 8)
+    VT_KNN_CASE(64, 8)
     default:
       return fail(VOTESS_EINVAL, "knn: k=%d has no kernel (k must be one of 8,12,16,24,32,48,64)", k);
   }
@@ -175,16 +306,16 @@ votess_status dispatch_k(int k, const void* sorted, int n, const GridDev& G, con
 }  // namespace
 
 votess_status launch_knn(votess_ctx* ctx, const void* sorted, votess_dtype dt, int n, const GridDev& G,
-                         const int32_t* cell_start, const int32_t* queries, int nq, int k, votess_dtype dist,
-                         int32_t* knn, hipStream_t st) {
+                         const int32_t* cell_start, const SubGrid& sub, const int32_t* queries, int nq, int k,
+                         votess_dtype dist, int32_t* knn, hipStream_t st) {
   if (nq == 0) return VOTESS_OK;
   if (dt == VOTESS_F64 && dist == VOTESS_F32)
     return fail(VOTESS_EINVAL, "knn: F32 distances need F32 positions");
   if (dt == VOTESS_F32) {
-    if (dist == VOTESS_F32) return dispatch_k<float, float>(k, sorted, n, G, cell_start, queries, nq, knn, ctx->d_err, st);
-    return dispatch_k<float, double>(k, sorted, n, G, cell_start, queries, nq, knn, ctx->d_err, st);
+    if (dist == VOTESS_F32) return dispatch_k<float, float>(k, sorted, n, G, cell_start, sub, queries, nq, knn, ctx->d_err, st);
+    return dispatch_k<float, double>(k, sorted, n, G, cell_start, sub, queries, nq, knn, ctx->d_err, st);
   }
-  return dispatch_k<double, double>(k, sorted, n, G, cell_start, queries, nq, knn, ctx->d_err, st);
+  return dispatch_k<double, double>(k, sorted, n, G, cell_start, sub, queries, nq, knn, ctx->d_err, st);
 }
 
 }  // namespace votess

@@ -467,11 +467,11 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
 }  // namespace
 
 votess_status run_features(votess_ctx* ctx, const void* sorted, votess_dtype dt, int n, const GridDev& G,
-                           const int32_t* cell_start, const int32_t* queries, int nq, int32_t* knn16, float* feats,
-                           hipStream_t st) {
+                           const int32_t* cell_start, const SubGrid& sub, const int32_t* queries, int nq,
+                           int32_t* knn16, float* feats, hipStream_t st) {
   if (nq == 0) return VOTESS_OK;
-  VT_TRY(launch_knn(ctx, sorted, dt, n, G, cell_start, queries, nq, 16, dt == VOTESS_F32 ? VOTESS_F32 : VOTESS_F64,
-                    knn16, st));
+  VT_TRY(launch_knn(ctx, sorted, dt, n, G, cell_start, sub, queries, nq, 16,
+                    dt == VOTESS_F32 ? VOTESS_F32 : VOTESS_F64, knn16, st));
   const unsigned b = (unsigned)((nq + 255) / 256);
   if (dt == VOTESS_F32)
     k_features<float><<<b, 256, 0, st>>>((const float4*)sorted, n, G, cell_start, queries, nq, knn16, feats);
@@ -549,8 +549,8 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
   (void)hipEventCreate(&e1);
   (void)hipEventCreate(&e2);
   (void)hipEventRecord(e0, st);
-  votess_status rc = run_features(ctx, sorted, base.dtype, n, G, cell_start, nullptr, n, (int32_t*)knn16,
-                                  (float*)feats, st);
+  votess_status rc = run_features(ctx, sorted, base.dtype, n, G, cell_start, base.sub, nullptr, n,
+                                  (int32_t*)knn16, (float*)feats, st);
   (void)hipEventRecord(e1, st);
   if (rc == VOTESS_OK) rc = run_choose(km, (const float*)feats, n, (float)tau, (uint8_t*)bucket, nullptr, st);
   (void)hipEventRecord(e2, st);
@@ -575,7 +575,7 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
     if (cnt == 0) continue;
     const int k = votess_buckets[b];
     (void)hipEventRecord(e0, st);
-    rc = launch_knn(ctx, sorted, base.dtype, n, G, cell_start, cells_buf, cnt, k, dist, (int32_t*)knnb, st);
+    rc = launch_knn(ctx, sorted, base.dtype, n, G, cell_start, base.sub, cells_buf, cnt, k, dist, (int32_t*)knnb, st);
     (void)hipEventRecord(e1, st);
     if (rc != VOTESS_OK) break;
     ClipLaunch c = base;
@@ -702,18 +702,22 @@ votess_status votess_kmodel_get_params(votess_kmodel* km, float* params_h, float
 }
 
 votess_status votess_features(votess_ctx* ctx, const void* sorted, int64_t n, const votess_grid* grid,
-                              const int32_t* cell_start, const int32_t* queries, int64_t nq, float* feats,
-                              void* stream) {
+                              const int32_t* cell_start, const int32_t* subinfo, const int32_t* sub_start,
+                              const int32_t* queries, int64_t nq, float* feats, void* stream) {
   if (!ctx || !grid) return fail(VOTESS_EINVAL, "features: null ctx/grid");
   if (!queries) nq = n;
   if (n < 1 || nq < 0 || n >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "features: bad sizes");
   if (nq > 0 && (!sorted || !cell_start || !feats)) return fail(VOTESS_EINVAL, "features: null buffer");
+  VT_TRY(check_sub(subinfo, sub_start, n, "features"));
   VT_HIP(hipSetDevice(ctx->device));
   void* knn16 = dev_alloc(ctx, (size_t)std::max<int64_t>(nq, 1) * 16 * 4);
   if (!knn16) return fail(VOTESS_ENOMEM, "features: 16-NN buffer");
   hipStream_t st = (hipStream_t)stream;
-  votess_status rc =
-      run_features(ctx, sorted, VOTESS_F32, (int)n, to_dev(*grid), cell_start, queries, (int)nq, (int32_t*)knn16, feats, st);
+  SubGrid sg;
+  sg.info = (const int2*)subinfo;
+  sg.start = sub_start;
+  votess_status rc = run_features(ctx, sorted, VOTESS_F32, (int)n, to_dev(*grid), cell_start, sg, queries, (int)nq,
+                                  (int32_t*)knn16, feats, st);
   (void)hipStreamSynchronize(st);
   dev_free(ctx, knn16);
   return rc;

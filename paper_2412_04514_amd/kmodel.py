@@ -102,13 +102,14 @@ class KModel:
 
 def features(sorted_, grid, cell_start, queries=None, ctx=None) -> torch.Tensor:
     """12 features per query (F32 sorted points)."""
-    from . import Context
+    from . import Context, _grid_c, _sub
     ctx = ctx or Context.get()
     n = sorted_.shape[0]
     nq = n if queries is None else queries.shape[0]
     out = torch.empty(max(nq, 1), NFEAT, dtype=torch.float32, device=sorted_.device)
-    check(ctx.lib.votess_features(ctx.handle, _ptr(sorted_), n, C.byref(grid), _ptr(cell_start), _ptr(queries), nq,
-                                  _ptr(out), _stream()))
+    si, ss = _sub(grid)
+    check(ctx.lib.votess_features(ctx.handle, _ptr(sorted_), n, C.byref(_grid_c(grid)), _ptr(cell_start), si, ss,
+                                  _ptr(queries), nq, _ptr(out), _stream()))
     return out[:nq]
 
 

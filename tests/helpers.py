@@ -51,3 +51,47 @@ def volume_errors(gpu_vol, orc_vol, prec: str, box_vol: float = 1.0, rows=None):
 def vertex_map(vrow_ptr, vxyz, vplanes, i):
     a, b = int(vrow_ptr[i]), int(vrow_ptr[i + 1])
     return {tuple(sorted(int(x) for x in vplanes[k])): np.asarray(vxyz[k]) for k in range(a, b)}
+
+
+def triple_vertices(P, owner, vplanes, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    """Each vertex as the meeting point of its three planes, solved by
+    Cramer's rule in long double (64-bit mantissa), and the conditioning
+    kappa = |n_a| |n_b| |n_c| / |det| of the three plane normals.
+
+    Plane ids: q >= 0 is the bisector of the owner and point q (normal
+    P[q] - P[i], offset |P[q] - P[i]|^2 / 2 relative to P[i]); -1..-6 are
+    the box walls x-, x+, y-, y+, z-, z+."""
+    L = np.longdouble
+    P = np.asarray(P, dtype=np.float64)
+    vplanes = np.asarray(vplanes)
+    pi = P[owner].astype(L)
+    nv = len(owner)
+    n = np.zeros((nv, 3, 3), L)
+    r = np.zeros((nv, 3), L)
+    lo_, hi_ = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    for c in range(3):
+        q = vplanes[:, c]
+        nb = q >= 0
+        d = P[np.where(nb, q, 0)].astype(L) - pi
+        n[nb, c] = d[nb]
+        r[nb, c] = (d[nb] ** 2).sum(1) / 2
+        w = np.nonzero(~nb)[0]
+        ax = (-q[w] - 1) // 2
+        wall = np.where((-q[w] - 1) % 2 == 1, hi_[ax], lo_[ax]).astype(L)
+        n[w, c, ax] = 1
+        r[w, c] = wall - pi[w, ax]
+
+    def det(m):
+        a, b, cc = m[:, 0], m[:, 1], m[:, 2]
+        return (a[:, 0] * (b[:, 1] * cc[:, 2] - b[:, 2] * cc[:, 1]) - a[:, 1] * (b[:, 0] * cc[:, 2] - b[:, 2] * cc[:, 0])
+                + a[:, 2] * (b[:, 0] * cc[:, 1] - b[:, 1] * cc[:, 0]))
+
+    D = det(n)
+    y = np.zeros((nv, 3), L)
+    with np.errstate(divide="ignore", invalid="ignore"):  # singular triples give inf/nan
+        for k in range(3):
+            m = n.copy()
+            m[:, :, k] = r
+            y[:, k] = det(m) / D
+        kappa = np.sqrt((n.astype(np.float64) ** 2).sum(2)).prod(1) / np.abs(D.astype(np.float64))
+    return (y + pi).astype(np.float64), kappa

@@ -72,8 +72,8 @@ def test_host_side_validation():
     assert b"box" in lib.votess_last_error()
     ok = _lib.Box((0, 0, 0), (1, 1, 1))
     assert lib.votess_grid_plan(-1, C.byref(ok), 2.0, C.byref(grid)) == 1
-    assert lib.votess_grid_sort(None, None, 0, 10, C.byref(ok), C.byref(grid), None, None, None, None) == 1
-    assert lib.votess_knn(None, None, 0, 10, C.byref(grid), None, None, 10, 32, 0, None, None) == 1
+    assert lib.votess_grid_sort(None, None, 0, 10, C.byref(ok), C.byref(grid), None, None, None, None, None, None) == 1
+    assert lib.votess_knn(None, None, 0, 10, C.byref(grid), None, None, None, None, 10, 32, 0, None, None) == 1
     opts = _lib.ClipOpts()
     assert lib.votess_clip_cells(None, None, 0, 10, C.byref(ok), None, 10, None, 32, C.byref(opts),
                                  *([None] * 9)) == 1

@@ -251,3 +251,27 @@ def test_kneeded_monotone_and_work():
     assert oracle.kneeded(np.array([[0.3, 0.4, 0.5]]))["kneeded"].tolist() == [0]
     two = oracle.kneeded(np.array([[0.3, 0.5, 0.5], [0.7, 0.5, 0.5]]))["kneeded"]
     assert two.tolist() == [1, 1]
+
+
+def test_oracle_vertices_meet_their_three_planes():
+    """Each oracle vertex lies where the three planes it names meet (solved
+    in long double): the edge interpolation keeps the geometry it reports."""
+    from helpers import triple_vertices
+    P = gen.cluster(4000, seed=21, dtype=np.float32, n_clusters=16).astype(np.float64)
+    o = oracle.tessellate(P, vertices=True)
+    owner = np.repeat(np.arange(len(P)), np.diff(o["vrow_ptr"]))
+    ref, kappa = triple_vertices(P, owner, o["vplanes"])
+    R = np.zeros(len(P))
+    np.maximum.at(R, owner, np.abs(ref - P[owner]).max(1))
+    rel = np.abs(o["vxyz"] - ref).max(1) / R[owner]
+    assert np.median(rel) <= 1e-15 and rel.max() <= 1e-9
+    # the order in which the three planes are named does not matter ...
+    swapped = o["vplanes"][:, [1, 0, 2]]
+    ref2, _ = triple_vertices(P, owner, swapped)
+    assert np.allclose(ref2, ref, rtol=0, atol=1e-12)
+    # ... but a wrong plane does: each vertex moves off when one id is replaced
+    wrong = o["vplanes"].copy()
+    wrong[:, 0] = (owner + len(P) // 2) % len(P)
+    ref3, _ = triple_vertices(P, owner, wrong)
+    moved = np.abs(ref3 - o["vxyz"]).max(1) / R[owner]
+    assert np.median(np.nan_to_num(moved, nan=np.inf)) > 1e-3  # singular triples count as moved
