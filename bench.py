@@ -51,6 +51,9 @@ def main(argv=None) -> int:
     ap.add_argument("--no-baseline-f64", action="store_true")
     ap.add_argument("--mode", choices=["auto", "fixed", "learned"], default="auto")
     ap.add_argument("--k0", type=int, default=32)
+    ap.add_argument("--retries", type=int, default=0,
+                    help="doublings of k after the learned pass (64 -> 128 -> 256) before the stream phase; "
+                         "0: the learned pass streams its uncertified cells directly")
     ap.add_argument("--profile-step", action="store_true", help="one headline step only (for rocprofv3)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -75,7 +78,7 @@ def main(argv=None) -> int:
     if args.mode in ("auto", "learned"):
         try:
             from paper_2412_04514_amd import kmodel as km
-            kmodel = km.load_default(args.workload)
+            kmodel = km.load_default(args.workload, max_gpu_retries=args.retries)
         except Exception as e:  # no trained model shipped for this workload
             if args.mode == "learned":
                 raise
@@ -83,7 +86,7 @@ def main(argv=None) -> int:
     headline = dict(precision="f32", k0=args.k0, max_gpu_retries=1)
     label = "fixed-k FP32"
     if kmodel is not None:
-        headline = dict(precision="f32", kmodel=kmodel, tau=kmodel.tau)
+        headline = dict(precision="f32", kmodel=kmodel, tau=kmodel.tau, max_gpu_retries=args.retries)
         label = "learned-k FP32"
 
     def run(cfg, steps, warmup, tag):

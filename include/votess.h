@@ -160,7 +160,7 @@ VOTESS_API int64_t votess_sub_capacity(int64_t n);
  *   dist       arithmetic of the squared distances: F64, or F32 (F32 input only)
  *   knn        [nq,k] int32 out: sorted indices ascending by (d^2, sorted index),
  *              padded with -1 when fewer than k other points exist
- * k is one of 8, 12, 16, 24, 32, 48, 64.  A zero distance raises device error
+ * k is one of 8, 12, 16, 24, 32, 48, 64, 128, 256.  A zero distance raises device error
  * bit 2 (duplicate). */
 VOTESS_API votess_status votess_knn(votess_ctx* ctx, const void* sorted, votess_dtype dtype, int64_t n,
                          const votess_grid* grid, const int32_t* cell_start, const int32_t* subinfo,
@@ -213,7 +213,8 @@ typedef struct votess_kmodel votess_kmodel;
 
 typedef struct {
   int32_t k0;               /* first list size (default 32) */
-  int32_t max_gpu_retries;  /* doublings of k on the GPU after the first pass (default 1) */
+  int32_t max_gpu_retries;  /* doublings of k on the GPU after the first pass, up to k = 256
+                               (default 1; the learned first pass ends at k = 64) */
   double pts_per_cell;      /* grid density (default 2) */
   votess_precision precision;
   double eps;               /* default 1e-6 */

@@ -102,7 +102,7 @@ votess_status check_box(const votess_box* box) {
 }
 
 bool valid_k(int k) {
-  return k == 8 || k == 12 || k == 16 || k == 24 || k == 32 || k == 48 || k == 64;
+  return k == 8 || k == 12 || k == 16 || k == 24 || k == 32 || k == 48 || k == 64 || k == 128 || k == kMaxK;
 }
 
 struct Timer {
@@ -254,7 +254,7 @@ votess_status votess_knn(votess_ctx* ctx, const void* sorted, votess_dtype dtype
                          int32_t* knn, void* stream) {
   if (!ctx) return fail(VOTESS_EINVAL, "ctx is null");
   VT_TRY(check_grid(grid));
-  if (!valid_k(k)) return fail(VOTESS_EINVAL, "knn: k=%d not in {8,12,16,24,32,48,64}", k);
+  if (!valid_k(k)) return fail(VOTESS_EINVAL, "knn: k=%d not in {8,12,16,24,32,48,64,128,256}", k);
   if (!queries) nq = n;
   if (n < 0 || nq < 0 || n >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "knn: bad sizes");
   if (nq > 0 && (!sorted || !cell_start || !knn)) return fail(VOTESS_EINVAL, "knn: null buffer");
@@ -365,7 +365,7 @@ void votess_result_free(votess_ctx* ctx, votess_result* r) {
 namespace votess {
 votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau, const void* sorted, int n,
                                  const votess_grid& grid, const int32_t* cell_start, const ClipLaunch& base,
-                                 int32_t* knn_buf, int32_t* cells_buf, votess_stats& S, hipStream_t st);
+                                 int stream, int32_t* cells_buf, votess_stats& S, hipStream_t st);
 }
 
 namespace {
@@ -476,8 +476,11 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   const SubGrid SG = base.sub;
   // the last list pass on the GPU streams uncertified cells on by grid rings
   const bool stream_last = P.gpu_stream != 0 && P.force_fail_every == 0;
+  // doublings of k after the first pass (the learned pass ends at the
+  // largest bucket), up to the largest k-NN kernel
+  const int k_first = P.kmodel ? 64 : P.k0;
   int nretry = 0;
-  for (int kk = P.k0; nretry < P.max_gpu_retries && kk < 64; ++nretry) kk = std::min(2 * kk, 64);
+  for (int kk = k_first; nretry < P.max_gpu_retries && kk < kMaxK; ++nretry) kk = std::min(2 * kk, kMaxK);
 
   // ---- first pass over all cells
   int k = P.k0;
@@ -486,8 +489,8 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   int32_t* nxt = cells2.get<int32_t>();
   if (n > 0) {
     if (P.kmodel) {
-      VT_TRY(learned_first_pass(ctx, P.kmodel, P.tau, sorted.p, n, grid, cell_start.get<int32_t>(), base, nullptr,
-                                cur, S, st));
+      VT_TRY(learned_first_pass(ctx, P.kmodel, P.tau, sorted.p, n, grid, cell_start.get<int32_t>(), base,
+                                stream_last && nretry == 0, cur, S, st));
       k = 64;  // retries of the learned pass continue from the largest bucket
     } else {
       VT_TRY(alloc_buf(ctx, knn, nn * (size_t)k * 4));
@@ -520,11 +523,11 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
                                  (1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY), st));
     VT_HIP(hipMemcpyAsync(&nfail, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
     VT_HIP(hipStreamSynchronize(st));
-    if (!P.kmodel) S.pass_failed[S.npasses++] = nfail;
+    if (!P.kmodel && S.npasses < VOTESS_MAX_PASSES) S.pass_failed[S.npasses++] = nfail;
   }
   // ---- GPU retry ladder: cells whose radius test failed retry at doubled k;
   // cells that overflowed the fast kernel rerun in the large-capacity kernel
-  auto capacity_pass = [&](const int32_t* ids, int cnt, int kk) -> votess_status {
+  auto capacity_pass = [&](const int32_t* ids, int cnt, int kk, bool strm) -> votess_status {
     int ncap = 0;
     VT_TRY(launch_compact_failed(status.get<uint8_t>(), ids, cnt, nxt, ctx->d_counter, 1u << VOTESS_CELL_CAPACITY,
                                  st));
@@ -546,11 +549,11 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     c2.knn = knn2.get<int32_t>();
     c2.k = kk;
     c2.capacity = 1;
-    c2.stream = stream_last;
+    c2.stream = strm ? 1 : 0;
     return launch_clip(c2, st);
   };
-  for (int r = 0; r < nretry && nfail > 0 && P.force_fail_every == 0 && k < 64; ++r) {
-    k = std::min(2 * k, 64);
+  for (int r = 0; r < nretry && nfail > 0 && P.force_fail_every == 0 && k < kMaxK; ++r) {
+    k = std::min(2 * k, kMaxK);
     VT_TRY(alloc_buf(ctx, knn, (size_t)nfail * k * 4));
     {
       Timer T(st, &S.ms_knn);
@@ -567,18 +570,21 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
       c.stream = stream_last && r == nretry - 1;
       VT_TRY(launch_clip(c, st));
     }
-    VT_TRY(capacity_pass(cur, nfail, k));
-    S.pass_k[S.npasses] = k;
-    S.pass_cells[S.npasses] = nfail;
+    VT_TRY(capacity_pass(cur, nfail, k, stream_last && r == nretry - 1));
+    const int cells_in = nfail;
     VT_TRY(launch_compact_failed(status.get<uint8_t>(), cur, nfail, nxt, ctx->d_counter,
                                  (1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY), st));
     VT_HIP(hipMemcpyAsync(&nfail, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
     VT_HIP(hipStreamSynchronize(st));
-    S.pass_failed[S.npasses++] = nfail;
+    if (S.npasses < VOTESS_MAX_PASSES) {
+      S.pass_k[S.npasses] = k;
+      S.pass_cells[S.npasses] = cells_in;
+      S.pass_failed[S.npasses++] = nfail;
+    }
     std::swap(cur, nxt);
   }
   // capacity overflows that no retry revisited (no retries left, or k at its maximum)
-  if (nfail > 0 && P.force_fail_every == 0) VT_TRY(capacity_pass(cur, nfail, k));
+  if (nfail > 0 && P.force_fail_every == 0) VT_TRY(capacity_pass(cur, nfail, k, stream_last));
   // ---- everything not certified goes to the host
   int nhost = 0;
   if (n > 0) {

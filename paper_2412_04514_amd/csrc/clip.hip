@@ -127,6 +127,29 @@ __device__ __forceinline__ T shfl_xor_w(T v, int m, int w) {
   return __shfl_xor(v, m, w);
 }
 
+// FP64 plane of a cell (generator p): the bisector with point `id` (>= 0) or
+// box wall -id-1 (x-, x+, y-, y+, z-, z+); n . x <= c relative to p.  All
+// arguments are values, so that no selection below goes through memory.
+template <typename Rec4>
+__device__ __forceinline__ void plane64_of(int id, const Rec4* rec, double px, double py, double pz, double lo0,
+                                           double lo1, double lo2, double hi0, double hi1, double hi2, V3<double>& n,
+                                           double& c) {
+  if (id >= 0) {
+    const Rec4 q = rec[id];
+    n = {(double)q.x - px, (double)q.y - py, (double)q.z - pz};
+    c = 0.5 * dot(n, n);
+  } else {
+    const int w = -id - 1, ax = w >> 1;
+    const bool hi = w & 1;
+    const double lo_a = ax == 0 ? lo0 : (ax == 1 ? lo1 : lo2);
+    const double hi_a = ax == 0 ? hi0 : (ax == 1 ? hi1 : hi2);
+    const double p_a = ax == 0 ? px : (ax == 1 ? py : pz);
+    const double sgn = hi ? 1.0 : -1.0;
+    n = {ax == 0 ? sgn : 0.0, ax == 1 ? sgn : 0.0, ax == 2 ? sgn : 0.0};
+    c = hi ? hi_a - p_a : p_a - lo_a;
+  }
+}
+
 template <typename P, typename R, int L, int TMAX, int PMAX, bool RECHECK, bool STREAM>
 __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
   using Rec4 = typename Rec<P>::type;
@@ -146,6 +169,14 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
   __shared__ unsigned snew[G * PMAX];
   constexpr int TE = RECHECK ? G * TP : 1;
   __shared__ float verr[TE];  // forward error bound of each float vertex
+  // stream phase: vertex slots whose ball can reach the current grid row /
+  // dense cell (see below)
+  constexpr int RL = STREAM ? G * TMAX : 1;
+  __shared__ unsigned char relR[RL], relD[RL];
+  // stream phase: geometry of the dense cell being scanned (cell corner,
+  // sub-grid origin and sub-cell widths), per group
+  constexpr int DG = STREAM ? G * 9 : 1;
+  __shared__ double dgeo[DG];
 
   const Rec4* rec = (const Rec4*)a.rec;
   const int lane = threadIdx.x;
@@ -193,22 +224,9 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
   };
 
   // FP64 plane of slot f, from the exact inputs (used by the recheck).
+  const double blo0 = a.lo0, blo1 = a.lo1, blo2 = a.lo2, bhi0 = a.hi0, bhi1 = a.hi1, bhi2 = a.hi2;
   auto plane64 = [&](int f, V3<double>& n, double& c) {
-    const int id = pid[pb + f];
-    if (id >= 0) {
-      const Rec4 q = rec[id];
-      n = {(double)q.x - p64x, (double)q.y - p64y, (double)q.z - p64z};
-      c = 0.5 * dot(n, n);
-    } else {
-      const int w = -id - 1, ax = w >> 1;
-      const bool hi = w & 1;
-      const double lo_a = ax == 0 ? a.lo0 : (ax == 1 ? a.lo1 : a.lo2);
-      const double hi_a = ax == 0 ? a.hi0 : (ax == 1 ? a.hi1 : a.hi2);
-      const double p_a = ax == 0 ? p64x : (ax == 1 ? p64y : p64z);
-      const double sgn = hi ? 1.0 : -1.0;
-      n = {ax == 0 ? sgn : 0.0, ax == 1 ? sgn : 0.0, ax == 2 ? sgn : 0.0};
-      c = hi ? hi_a - p_a : p_a - lo_a;
-    }
+    plane64_of(pid[pb + f], rec, p64x, p64y, p64z, blo0, blo1, blo2, bhi0, bhi1, bhi2, n, c);
   };
   auto vertex64 = [&](unsigned u) -> V3<double> {
     V3<double> na, nb, nc;
@@ -647,10 +665,92 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     int myj = -1;
     R myd2 = R(0);
     const R skip_scale = RECHECK ? R(1) - R(2e-6) : R(1) - R(1e-12);
+    // box of the current vertices (relative to the seed, widened by their
+    // error bounds): a candidate d can cut only if some vertex v has
+    // d.v > |d|^2 / 2, and max_v d.v <= sum_a max(d_a lo_a, d_a hi_a).  The
+    // cell only shrinks, so an older box is still a valid bound.
+    R bl0 = 0, bl1 = 0, bl2 = 0, bh0 = 0, bh1 = 0, bh2 = 0;
+    bool box_ok = false;
+    auto vertex_box = [&]() {
+      R a0 = R(3.0e38), a1 = R(3.0e38), a2 = R(3.0e38), b0 = R(-3.0e38), b1 = R(-3.0e38), b2 = R(-3.0e38);
+      for (int t = j; t < H; t += L) {
+        if (tri[vb + t] == kEmpty) continue;
+        const R e = RECHECK ? (R)verr[vb + t] : R(0);
+        const R X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+        a0 = fmin(a0, X - e); b0 = fmax(b0, X + e);
+        a1 = fmin(a1, Y - e); b1 = fmax(b1, Y + e);
+        a2 = fmin(a2, Z - e); b2 = fmax(b2, Z + e);
+      }
+#pragma unroll
+      for (int o = 1; o < L; o <<= 1) {
+        a0 = fmin(a0, shfl_xor_w(a0, o, L)); b0 = fmax(b0, shfl_xor_w(b0, o, L));
+        a1 = fmin(a1, shfl_xor_w(a1, o, L)); b1 = fmax(b1, shfl_xor_w(b1, o, L));
+        a2 = fmin(a2, shfl_xor_w(a2, o, L)); b2 = fmax(b2, shfl_xor_w(b2, o, L));
+      }
+      bl0 = a0; bl1 = a1; bl2 = a2; bh0 = b0; bh1 = b1; bh2 = b2;
+    };
+    // relative slack of that test: above the rounding of the plane tests
+    // (and of the float path's rechecks)
+    const R sup_slack = RECHECK ? R(4e-6) : R(1e-12);
+    // A point cuts the cell iff it lies in the ball of some vertex v through
+    // the seed (centre v, radius |v|).  For a box of candidates (a grid row or
+    // a dense cell's sub-block), the vertices whose ball meets the box are
+    // listed in `out`; none: the box cannot hold a cutting point.  The balls
+    // are widened past rounding and the float path's vertex error bounds.
+    // Lists name vertex slots, so a cut (which reuses slots) invalidates them.
+    auto relevant = [&](unsigned char* out, double x0, double x1, double y0, double y1, double z0,
+                        double z1) -> int {
+      const double ax = x0 - p64x - gmarg, bx = x1 - p64x + gmarg;
+      const double ay = y0 - p64y - gmarg, by = y1 - p64y + gmarg;
+      const double az = z0 - p64z - gmarg, bz = z1 - p64z + gmarg;
+      unsigned bits = 0;
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2) {
+        const int t = j + L * s2;
+        if (t < H && tri[vb + t] != kEmpty) {
+          const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+          const double rv = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-5) + (RECHECK ? 4.0 * (double)verr[vb + t] : 0.0);
+          const double gx = fmax(0.0, fmax(ax - X, X - bx)), gy = fmax(0.0, fmax(ay - Y, Y - by)),
+                       gz = fmax(0.0, fmax(az - Z, Z - bz));
+          if (gx * gx + gy * gy + gz * gz <= rv * rv) bits |= 1u << s2;
+        }
+      }
+      int tot;
+      int w = gexcl(__popc(bits), tot);
+#pragma unroll
+      for (int s2 = 0; s2 < S; ++s2)
+        if ((bits >> s2) & 1u) out[g * TMAX + w++] = (unsigned char)(j + L * s2);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      return tot;
+    };
+    int nR = 0, nD = 0;
+    bool okR = false, okD = false;  // lists valid for the current vertices
+    // does a box of candidates meet the ball of a vertex of the dense cell's list?
+    auto dense_box_relevant = [&](double x0, double x1, double y0, double y1, double z0, double z1) -> bool {
+      if (!okD) return true;
+      const double ax = x0 - p64x - gmarg, bx = x1 - p64x + gmarg;
+      const double ay = y0 - p64y - gmarg, by = y1 - p64y + gmarg;
+      const double az = z0 - p64z - gmarg, bz = z1 - p64z + gmarg;
+      bool hit = false;
+      for (int i = j; i < nD && !hit; i += L) {
+        const int t = relD[g * TMAX + i];
+        const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+        const double rv = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-5) + (RECHECK ? 4.0 * (double)verr[vb + t] : 0.0);
+        const double gx = fmax(0.0, fmax(ax - X, X - bx)), gy = fmax(0.0, fmax(ay - Y, Y - by)),
+                     gz = fmax(0.0, fmax(az - Z, Z - bz));
+        hit = gx * gx + gy * gy + gz * gz <= rv * rv;
+      }
+      return group_any(hit);
+    };
+    bool rdense = false;  // the current range lies in a dense cell
     while (__any(strm && st == ST_RUN)) {
       const bool act = strm && st == ST_RUN;
       // refill this group's batch of candidates (group-uniform loop)
       if (act && pend == 0u) {
+        if (!box_ok) {
+          vertex_box();
+          box_ok = true;
+        }
         bool done = false;
         while (!done) {
           if (jcur >= jend) {
@@ -692,11 +792,24 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
                   if (++dy > dyhi) { dy = dylo; ++dz; }
                   continue;
                 }
+                if (sx0 <= sx1 && okD) {
+                  // skip the sub-row when no listed vertex ball reaches it
+                  const double* dgp = dgeo + g * 9;
+                  const int m2 = dst[2];
+                  const double X0 = sx0 == 0 ? dgp[0] : dgp[3] + sx0 * dgp[6];
+                  const double X1 = sx1 == dm0 - 1 ? dgp[0] + Gd.h0 : dgp[3] + (sx1 + 1) * dgp[6];
+                  const double Y0 = dy == 0 ? dgp[1] : dgp[4] + dy * dgp[7];
+                  const double Y1 = dy == dm1 - 1 ? dgp[1] + Gd.h1 : dgp[4] + (dy + 1) * dgp[7];
+                  const double Z0 = dz == 0 ? dgp[2] : dgp[5] + dz * dgp[8];
+                  const double Z1 = dz == m2 - 1 ? dgp[2] + Gd.h2 : dgp[5] + (dz + 1) * dgp[8];
+                  if (!dense_box_relevant(X0, X1, Y0, Y1, Z0, Z1)) sx1 = sx0 - 1;
+                }
                 if (sx0 <= sx1) {
                   const int rowb = kSubHead + dm0 * (dy + dm1 * dz);
                   jcur = dbase + dst[rowb + sx0];
                   jend = dbase + dst[rowb + sx1 + 1];
                   have_run = jcur < jend;
+                  rdense = true;
                 }
                 continue;
               }
@@ -711,6 +824,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
                   jend = a.cell_start[rrow + xe];
                   rx = xe;
                   have_run = jcur < jend;
+                  rdense = false;
                   continue;
                 }
                 // dense cell rx: its sub-cells inside the flower box
@@ -722,6 +836,30 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
                 dsy1 = sub_axis(fw3, sc.lo1, sc.ih1, sc.m1);
                 dsz0 = sub_axis(fw4, sc.lo2, sc.ih2, sc.m2);
                 dsz1 = sub_axis(fw5, sc.lo2, sc.ih2, sc.m2);
+                {
+                  // the sub-block's box (edge sub-cells reach the cell's faces)
+                  const double cxl = Gd.lo0 + rx * Gd.h0, cyl = Gd.lo1 + yy * Gd.h1, czl = Gd.lo2 + zz * Gd.h2;
+                  const double w0 = 1.0 / sc.ih0, w1 = 1.0 / sc.ih1, w2 = 1.0 / sc.ih2;
+                  const double X0 = dsx0 == 0 ? cxl : sc.lo0 + dsx0 * w0;
+                  const double X1 = dsx1 == sc.m0 - 1 ? cxl + Gd.h0 : sc.lo0 + (dsx1 + 1) * w0;
+                  const double Y0 = dsy0 == 0 ? cyl : sc.lo1 + dsy0 * w1;
+                  const double Y1 = dsy1 == sc.m1 - 1 ? cyl + Gd.h1 : sc.lo1 + (dsy1 + 1) * w1;
+                  const double Z0 = dsz0 == 0 ? czl : sc.lo2 + dsz0 * w2;
+                  const double Z1 = dsz1 == sc.m2 - 1 ? czl + Gd.h2 : sc.lo2 + (dsz1 + 1) * w2;
+                  nD = relevant(relD, X0, X1, Y0, Y1, Z0, Z1);
+                  okD = true;
+                  if (j == 0) {
+                    double* dgp = dgeo + g * 9;
+                    dgp[0] = cxl; dgp[1] = cyl; dgp[2] = czl;
+                    dgp[3] = sc.lo0; dgp[4] = sc.lo1; dgp[5] = sc.lo2;
+                    dgp[6] = w0; dgp[7] = w1; dgp[8] = w2;
+                  }
+                  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                  if (nD == 0) {
+                    ++rx;
+                    continue;
+                  }
+                }
                 dq0 = min(max(sub_axis(p64x, sc.lo0, sc.ih0, sc.m0), dsx0), dsx1);
                 dq1 = min(max(sub_axis(p64y, sc.lo1, sc.ih1, sc.m1), dsy0), dsy1);
                 dq2 = min(max(sub_axis(p64z, sc.lo2, sc.ih2, sc.m2), dsz0), dsz1);
@@ -769,9 +907,14 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
                 continue;
               }
               if (x0 <= x1) {
-                rrow = Gd.g0 * (yy + Gd.g1 * zz);
-                rx = x0;
-                rx1 = x1;
+                const double Y0 = Gd.lo1 + yy * Gd.h1, Z0 = Gd.lo2 + zz * Gd.h2;
+                nR = relevant(relR, Gd.lo0 + x0 * Gd.h0, Gd.lo0 + (x1 + 1) * Gd.h0, Y0, Y0 + Gd.h1, Z0, Z0 + Gd.h2);
+                okR = true;
+                if (nR > 0) {
+                  rrow = Gd.g0 * (yy + Gd.g1 * zz);
+                  rx = x0;
+                  rx1 = x1;
+                }
               }
             }
             if (done) break;
@@ -785,6 +928,37 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
             const R d2c = dist2_nc((R)q.x - px, (R)q.y - py, (R)q.z - pz);
             const bool beyond_list = d2c > dk2 || (d2c == dk2 && jj > ik);
             pass = beyond_list && d2c * skip_scale <= R(4) * (RECHECK ? (R)R2hi : R2);
+            if (pass) {
+              const R ex = (R)q.x - px, ey = (R)q.y - py, ez = (R)q.z - pz;
+              const R sup = fmax(ex * bl0, ex * bh0) + fmax(ey * bl1, ey * bh1) + fmax(ez * bl2, ez * bh2);
+              const R mag = fabs(ex) * fmax(fabs(bl0), fabs(bh0)) + fabs(ey) * fmax(fabs(bl1), fabs(bh1)) +
+                            fabs(ez) * fmax(fabs(bl2), fabs(bh2));
+              pass = sup >= R(0.5) * d2c - sup_slack * (mag + d2c);
+              if (pass) {
+                // exact: some vertex on the far side of the bisector (up to
+                // the plane test's own uncertainty window), against the
+                // vertices listed for this range, or all of them
+                const R cc = R(0.5) * d2c;
+                const R nrm1 = fabs(ex) + fabs(ey) + fabs(ez);
+                auto side = [&](int t) -> bool {
+                  const R X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+                  const R sv = ex * X + ey * Y + ez * Z - cc;
+                  const R scale = fabs(ex * X) + fabs(ey * Y) + fabs(ez * Z) + cc;
+                  const R win = RECHECK ? (R)a.eps * scale + nrm1 * (R)verr[vb + t] : R(1e-12) * scale;
+                  return sv > -win;
+                };
+                bool cuts = false;
+                if (rdense ? okD : okR) {
+                  const unsigned char* rl = rdense ? relD : relR;
+                  const int nr = rdense ? nD : nR;
+                  for (int i = 0; i < nr && !cuts; ++i) cuts = side(rl[g * TMAX + i]);
+                } else {
+                  for (int t = 0; t < H && !cuts; ++t)
+                    if (tri[vb + t] != kEmpty) cuts = side(t);
+                }
+                pass = cuts;
+              }
+            }
             myj = jj;
             myd2 = d2c;
           }
@@ -821,7 +995,12 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
         // the radius may have shrunk since the batch was filtered
         if (d2 * skip_scale > R(4) * (RECHECK ? (R)R2hi : R2)) run2 = false;
       }
+      const M alive_prev = alive;
       apply_plane(run2, nx, ny, nz, c, d2, nb2);
+      if (alive != alive_prev) {
+        box_ok = false;
+        okR = okD = false;
+      }
     }
     if (strm && st == VOTESS_CELL_CERTIFIED && j == 0 && a.counters) atomicAdd(&a.counters[4], 1ull);
   }

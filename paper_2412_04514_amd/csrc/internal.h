@@ -16,6 +16,8 @@ namespace votess {
 
 // ------------------------------------------------------------------ errors
 votess_status fail(votess_status s, const char* fmt, ...);
+// Largest list length of the k-NN kernels (the GPU retry ladder stops there).
+constexpr int kMaxK = 256;
 // Sub-grid buffers of votess_grid_sort: both or neither, 16-byte aligned.
 votess_status check_sub(const int32_t* subinfo, const int32_t* sub_start, int64_t n, const char* where);
 #define VT_HIP(call)                                                                 \

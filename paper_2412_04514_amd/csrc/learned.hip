@@ -523,11 +523,12 @@ static votess_status run_grad(votess_kmodel* km, const float* feats, const uint8
 }
 
 // Learned first pass of votess_tessellate: 16-NN + features, network choice
-// of a bucket per cell, then per bucket a k-NN pass and a clip pass with the
-// stream phase (cells the list does not certify keep clipping on the GPU).
+// of a bucket per cell, then per bucket a k-NN pass and a clip pass; with
+// `stream` the clip pass goes on by grid rings where the list does not
+// certify (else those cells are left for the retry ladder).
 votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau, const void* sorted, int n,
                                  const votess_grid& grid, const int32_t* cell_start, const ClipLaunch& base,
-                                 int32_t*, int32_t* cells_buf, votess_stats& S, hipStream_t st) {
+                                 int stream, int32_t* cells_buf, votess_stats& S, hipStream_t st) {
   const GridDev G = to_dev(grid);
   const votess_dtype dist = base.knn_dist;
   void* knn16 = dev_alloc(ctx, (size_t)n * 16 * 4);
@@ -583,7 +584,7 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
     c.nc = cnt;
     c.knn = (const int32_t*)knnb;
     c.k = k;
-    c.stream = 1;
+    c.stream = stream;
     rc = launch_clip(c, st);
     (void)hipEventRecord(e2, st);
     (void)hipEventSynchronize(e2);

@@ -169,16 +169,19 @@ def train(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), n_train: int = 1 << 
     return model
 
 
-def tune_tau(model: KModel, points: torch.Tensor, taus=(0.5, 0.7, 0.8, 0.9, 0.95), precision="f32", log=None):
+def tune_tau(model: KModel, points: torch.Tensor, taus=(0.5, 0.7, 0.8, 0.9, 0.95), precision="f32", log=None,
+             max_gpu_retries: int = 0):
     """Picks the threshold with the fastest learned tessellation of ``points``
-    (a validation set, not the evaluation input)."""
+    (a validation set, not the evaluation input), with the given number of
+    k doublings after the learned pass."""
     from . import tessellate
     best = None
+    kw = dict(precision=precision, kmodel=model, max_gpu_retries=max_gpu_retries)
     for tau in taus:
-        tessellate(points, precision=precision, kmodel=model, tau=tau)  # warm
+        tessellate(points, tau=tau, **kw)  # warm
         torch.cuda.synchronize()
         t = time.perf_counter()
-        tessellate(points, precision=precision, kmodel=model, tau=tau)
+        tessellate(points, tau=tau, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         if log:
@@ -192,15 +195,17 @@ def tune_tau(model: KModel, points: torch.Tensor, taus=(0.5, 0.7, 0.8, 0.9, 0.95
 _cache: dict = {}
 
 
-def load_default(workload: str, log=None) -> KModel:
+def load_default(workload: str, log=None, max_gpu_retries: int = 0) -> KModel:
     """A model for a named workload: trained on 2^21 cells of the workload's
-    seed-1 point set, tau tuned on that set (the evaluation input is seed 0)."""
-    if workload in _cache:
-        return _cache[workload]
+    seed-1 point set, tau tuned on that set (the evaluation input is seed 0)
+    for runs with ``max_gpu_retries`` doublings of k after the learned pass."""
+    key = (workload, max_gpu_retries)
+    if key in _cache:
+        return _cache[key]
     from . import gen
     P = torch.from_numpy(gen.make(workload, seed=1)).cuda()
     model = train(P, log=log)
-    tune_tau(model, P, log=log)
+    tune_tau(model, P, log=log, max_gpu_retries=max_gpu_retries)
     del P
-    _cache[workload] = model
+    _cache[key] = model
     return model

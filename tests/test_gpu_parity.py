@@ -144,7 +144,7 @@ def _knn_ref(S, queries, k, dist):
 
 @pytest.mark.parametrize("kind,dt", [("uniform", np.float64), ("cluster", np.float32), ("filament", np.float32),
                                      ("cluster64", np.float32)])
-@pytest.mark.parametrize("k", [8, 24, 64])
+@pytest.mark.parametrize("k", [8, 24, 64, 256])
 def test_knn_f64_exact(kind, dt, k):
     """cluster64: 64 clusters, 89% of the points in cells with sub-grids (m up to 5)."""
     note(f"knn f64 {kind} k={k}")
