@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 # 20000-cell sample with `python -m oracle.work_figures <workload> 20000`.
 ALGO_FLOPS_PER_CELL = {"cluster-16m-f32": 32586.95}
 
+# HBM bytes moved by all k_clip launches of one learned-k step, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (profiles/clip_traffic_cluster16m_f32.md).
+# Valid for the clip kernel as it was measured: re-measure after changing it.
+TRAFFIC_BYTES_PER_STEP = {"cluster-16m-f32": 3.461e10}
+
 PEAK = {"hbm_gbs": 8000.0, "fp32_tflops": 157.3, "fp64_tflops": 78.6}
 SORT_BYTES_PER_POINT = {np.float32: 12 + 16 + 4, np.float64: 24 + 32 + 4}  # read pts, write record + perm
 
@@ -55,6 +60,8 @@ def main(argv=None) -> int:
                     help="doublings of k after the learned pass (64 -> 128 -> 256) before the stream phase; "
                          "0: the learned pass streams its uncertified cells directly")
     ap.add_argument("--profile-step", action="store_true", help="one headline step only (for rocprofv3)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB on the device (calibrates rocprofv3 byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the tessellation has no multi-GPU path here.",
@@ -73,6 +80,11 @@ def main(argv=None) -> int:
     log(f"[bench] {args.workload}: {n} points generated in {time.time() - t0:.1f}s")
     pts = torch.from_numpy(P).to(dev)
     torch.cuda.synchronize()
+    if args.copy_probe_mib > 0:  # one plain device-to-device copy of known size
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
 
     kmodel = None
     if args.mode in ("auto", "learned"):
@@ -127,8 +139,9 @@ def main(argv=None) -> int:
     if dom == "clip":
         flops = ALGO_FLOPS_PER_CELL.get(args.workload)
         ach = flops * n / (ms_clip / 1e3) / 1e12 if flops else None
+        traffic = TRAFFIC_BYTES_PER_STEP.get(args.workload) if kmodel is not None else None
         roof = dict(bound="alu", achieved=ach, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
-                    frac=(ach / PEAK["fp32_tflops"]) if ach else None, traffic=None,
+                    frac=(ach / PEAK["fp32_tflops"]) if ach else None, traffic=traffic,
                     kernel="k_clip (all launches of a step)",
                     per_unit=f"{flops} algorithmic flops per cell (oracle work count)")
     elif dom == "knn":

@@ -180,3 +180,46 @@ def test_learned_gain_over_fixed_k(trained):
          f"learned knn+clip {sl['ms_knn'] + sl['ms_clip'] + sl['ms_features'] + sl['ms_mlp']:.1f} ms, "
          f"fixed {sf['ms_knn'] + sf['ms_clip']:.1f} ms")
     assert tl < tf
+
+
+@pytest.mark.parametrize("cfg", ["learned-f32", "fixed-f64"])
+def test_full_size_sampled_parity(trained, cfg):
+    """The 16M clustered workload in the launch configurations the benchmark
+    times (learned-k FP32 streaming after its buckets; fixed-k FP64 with the
+    doubling retry): 3000 seeded cells against the oracle cell by cell, and
+    whole-output invariants (volumes fill the box, neighbours are mutual)."""
+    P = gen.make("cluster-16m-f32", seed=0)
+    pts = torch.from_numpy(P).cuda()
+    if cfg == "learned-f32":
+        kw = dict(precision="f32", kmodel=trained, tau=0.9, max_gpu_retries=0)
+        prec = "f32"
+    else:
+        kw = dict(precision="f64", k0=32, max_gpu_retries=1)
+        prec = "f64"
+    res = vt.tessellate(pts, **kw)
+    del pts
+    rp, col = res.row_ptr.cpu().numpy(), res.col.cpu().numpy()
+    vol = res.volume.cpu().numpy()
+    note(f"  {cfg}: passes {res.stats['passes']} streamed {res.stats['streamed_cells']} "
+         f"host {res.stats['fallback_cells']}")
+    assert res.stats["unresolved_cells"] == 0
+    # whole output: the cells tile the unit box; neighbour relation is symmetric
+    assert abs(vol.sum() - 1.0) <= (1e-9 if prec == "f64" else 1e-5)
+    n = len(P)
+    src = torch.repeat_interleave(torch.arange(n, device="cuda"), (res.row_ptr[1:] - res.row_ptr[:-1]).long())
+    c = res.col.long()
+    fwd, _ = torch.sort(src * n + c)
+    bwd, _ = torch.sort(c * n + src)
+    assert torch.equal(fwd, bwd)
+    del src, c, fwd, bwd
+    # sampled cells against the oracle
+    rng = np.random.default_rng(123)
+    cells = np.sort(rng.choice(len(P), 3000, replace=False))
+    orc = oracle.tessellate(P.astype(np.float64), cells=cells)
+    for i in cells:
+        got = col[rp[i]:rp[i + 1]]
+        want = orc["col"][orc["row_ptr"][i]:orc["row_ptr"][i + 1]]
+        assert np.array_equal(np.sort(got), want), i
+    viol, rel = volume_errors(vol, orc["volume"], prec, rows=cells)
+    note(f"  {cfg}: sampled max rel volume error {rel.max():.2e}")
+    assert not viol.any()
