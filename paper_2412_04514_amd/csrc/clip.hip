@@ -658,8 +658,9 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     // the x-run being split at dense cells, and the sub-block of the dense
     // cell being scanned (sub-cells that meet the flower box)
     int rx = 1, rx1 = 0, rrow = 0;
+    // dense cell rows: z and y outward from the seed's row (0, +1, -1, +2, ...)
     int dm = 0, dm0 = 0, dm1 = 0, dbase = 0, dsx0 = 0, dsx1 = -1, dsy0 = 0, dsy1 = -1, dsz0 = 0, dsz1 = -1;
-    int dq0 = 0, dq1 = 0, dq2 = 0, drs = -1, dz = 1, dzhi = 0, dy = 0, dylo = 0, dyhi = -1, dpart = 0;
+    int dq1 = 0, dq2 = 0, ky = 0, kz = 0, kyn = 0, kzn = 0;
     const int* dst = nullptr;
     unsigned pend = 0;
     int myj = -1;
@@ -760,57 +761,34 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
             bool have_run = false;
             while (!have_run) {
               if (dm > 0) {
-                // sub-rings around the sub-cell nearest the seed, inside the
-                // sub-block: nearer sub-cells first
-                if (dz > dzhi) {
-                  if (drs >= 0 && dq0 - drs <= dsx0 && dq0 + drs >= dsx1 && dq1 - drs <= dsy0 && dq1 + drs >= dsy1 &&
-                      dq2 - drs <= dsz0 && dq2 + drs >= dsz1) {
-                    dm = 0;
-                    continue;
-                  }
-                  ++drs;
-                  dz = max(dq2 - drs, dsz0);
-                  dzhi = min(dq2 + drs, dsz1);
-                  dylo = max(dq1 - drs, dsy0);
-                  dyhi = min(dq1 + drs, dsy1);
-                  dy = dylo;
-                  dpart = 0;
-                  if (dylo > dyhi) dz = dzhi + 1;
+                // the dense cell's sub-rows inside the flower box, one x-run
+                // each, rows nearer the seed first
+                if (kz >= kzn) {
+                  dm = 0;
                   continue;
                 }
-                const bool sface = dz == dq2 - drs || dz == dq2 + drs || dy == dq1 - drs || dy == dq1 + drs;
-                int sx0 = 1, sx1 = 0;
-                if (dpart == 0) {
-                  if (sface) { sx0 = max(dq0 - drs, dsx0); sx1 = min(dq0 + drs, dsx1); }
-                  else if (dq0 - drs >= dsx0) { sx0 = sx1 = dq0 - drs; }
-                  dpart = 1;
-                } else if (dpart == 1) {
-                  if (!sface && drs > 0 && dq0 + drs <= dsx1) { sx0 = sx1 = dq0 + drs; }
-                  dpart = 2;
-                } else {
-                  dpart = 0;
-                  if (++dy > dyhi) { dy = dylo; ++dz; }
-                  continue;
-                }
-                if (sx0 <= sx1 && okD) {
+                const int sz = dq2 + ((kz & 1) ? (kz + 1) >> 1 : -(kz >> 1));
+                const int sy = dq1 + ((ky & 1) ? (ky + 1) >> 1 : -(ky >> 1));
+                if (++ky >= kyn) { ky = 0; ++kz; }
+                if (sz < dsz0 || sz > dsz1 || sy < dsy0 || sy > dsy1) continue;
+                const int sx0 = dsx0, sx1 = dsx1;
+                if (okD) {
                   // skip the sub-row when no listed vertex ball reaches it
                   const double* dgp = dgeo + g * 9;
                   const int m2 = dst[2];
                   const double X0 = sx0 == 0 ? dgp[0] : dgp[3] + sx0 * dgp[6];
                   const double X1 = sx1 == dm0 - 1 ? dgp[0] + Gd.h0 : dgp[3] + (sx1 + 1) * dgp[6];
-                  const double Y0 = dy == 0 ? dgp[1] : dgp[4] + dy * dgp[7];
-                  const double Y1 = dy == dm1 - 1 ? dgp[1] + Gd.h1 : dgp[4] + (dy + 1) * dgp[7];
-                  const double Z0 = dz == 0 ? dgp[2] : dgp[5] + dz * dgp[8];
-                  const double Z1 = dz == m2 - 1 ? dgp[2] + Gd.h2 : dgp[5] + (dz + 1) * dgp[8];
-                  if (!dense_box_relevant(X0, X1, Y0, Y1, Z0, Z1)) sx1 = sx0 - 1;
+                  const double Y0 = sy == 0 ? dgp[1] : dgp[4] + sy * dgp[7];
+                  const double Y1 = sy == dm1 - 1 ? dgp[1] + Gd.h1 : dgp[4] + (sy + 1) * dgp[7];
+                  const double Z0 = sz == 0 ? dgp[2] : dgp[5] + sz * dgp[8];
+                  const double Z1 = sz == m2 - 1 ? dgp[2] + Gd.h2 : dgp[5] + (sz + 1) * dgp[8];
+                  if (!dense_box_relevant(X0, X1, Y0, Y1, Z0, Z1)) continue;
                 }
-                if (sx0 <= sx1) {
-                  const int rowb = kSubHead + dm0 * (dy + dm1 * dz);
-                  jcur = dbase + dst[rowb + sx0];
-                  jend = dbase + dst[rowb + sx1 + 1];
-                  have_run = jcur < jend;
-                  rdense = true;
-                }
+                const int rowb = kSubHead + dm0 * (sy + dm1 * sz);
+                jcur = dbase + dst[rowb + sx0];
+                jend = dbase + dst[rowb + sx1 + 1];
+                have_run = jcur < jend;
+                rdense = true;
                 continue;
               }
               if (rx <= rx1) {
@@ -860,17 +838,17 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
                     continue;
                   }
                 }
-                dq0 = min(max(sub_axis(p64x, sc.lo0, sc.ih0, sc.m0), dsx0), dsx1);
-                dq1 = min(max(sub_axis(p64y, sc.lo1, sc.ih1, sc.m1), dsy0), dsy1);
-                dq2 = min(max(sub_axis(p64z, sc.lo2, sc.ih2, sc.m2), dsz0), dsz1);
-                drs = -1;
-                dz = 1;
-                dzhi = 0;
                 dst = a.sub.start + info.x;
                 dbase = a.cell_start[rrow + rx];
                 dm = 1;
                 dm0 = sc.m0;
                 dm1 = sc.m1;
+                dq1 = min(max(sub_axis(p64y, sc.lo1, sc.ih1, sc.m1), dsy0), dsy1);
+                dq2 = min(max(sub_axis(p64z, sc.lo2, sc.ih2, sc.m2), dsz0), dsz1);
+                // offsets 0, +1, -1, ... up to the farther end of each range
+                kyn = 2 * max(dq1 - dsy0, dsy1 - dq1) + 1;
+                kzn = 2 * max(dq2 - dsz0, dsz1 - dq2) + 1;
+                ky = kz = 0;
                 ++rx;
                 continue;
               }
