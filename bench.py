@@ -106,15 +106,20 @@ def main(argv=None) -> int:
             vt.tessellate(pts, **cfg)
             log(f"[bench] {tag} warmup {i + 1}/{warmup}")
         torch.cuda.synchronize()
-        stats = []
+        stats, per = [], []
         t = time.perf_counter()
         for i in range(steps):
+            t1 = time.perf_counter()
             r = vt.tessellate(pts, **cfg)
+            torch.cuda.synchronize()
+            per.append((time.perf_counter() - t1) * 1e3)
             stats.append(r.stats)
             del r
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t) * 1e3 / steps
-        log(f"[bench] {tag}: {ms:.2f} ms/step")
+        log(f"[bench] {tag}: {ms:.2f} ms/step (median {np.median(per):.2f}, min {min(per):.2f})")
+        stats[-1]["_ms_median"] = float(np.median(per))
+        stats[-1]["_ms_min"] = float(min(per))
         return ms, stats
 
     ms, stats = run(headline, args.steps, args.warmup, label)
@@ -132,6 +137,10 @@ def main(argv=None) -> int:
                             "fixed-k FP64")
         base = dict(ms_per_step=ms64, cells_per_s=n / (ms64 / 1e3), knn_clip_ms=float(
             np.mean([s["ms_knn"] + s["ms_clip"] for s in stats64])), last_stats=stats64[-1])
+        # the same at fixed k = 64 (no retry), so that the gain is not measured against k = 32 alone
+        ms64b, stats64b = run(dict(precision="f64", k0=64, max_gpu_retries=0), max(1, args.steps // 2), 1,
+                              "fixed-k64 FP64")
+        base["k64_ms_per_step"] = ms64b
 
     # roofline of the dominant kernel (largest share of the step)
     work = {"sort": ms_sort, "knn": ms_knn + ms_feat, "clip": ms_clip}
@@ -162,6 +171,7 @@ def main(argv=None) -> int:
         cpu = cpu_baseline(P)
 
     knn_clip_ms = ms_knn + ms_clip + ms_feat + ms_mlp
+    gpu_ms = knn_clip_ms + ms_sort + mean("ms_assemble")
     out = {
         "metric": "Voronoi cells/sec at 16M pts (kNN+clip); learned-k FP32 vs fixed-k FP64 speedup",
         "value": n / (ms / 1e3),
@@ -178,9 +188,12 @@ def main(argv=None) -> int:
         "config": {"workload": args.workload, "points": n, "method": label, "box": "unit cube",
                    "parallelism": "single GPU"},
         "cells_per_s_knn_clip": n / (knn_clip_ms / 1e3),
+        "cells_per_s_gpu": n / (gpu_ms / 1e3),
+        "ms_step_median": st0.get("_ms_median"), "ms_step_min": st0.get("_ms_min"),
         "speedup_vs_fixed_k_f64": (base["ms_per_step"] / ms) if base else None,
         "fixed_k_f64": {"ms_per_step": base["ms_per_step"], "cells_per_s": base["cells_per_s"],
                         "knn_clip_ms": base["knn_clip_ms"]} if base else None,
+        "speedup_vs_fixed_k64_f64": (base["k64_ms_per_step"] / ms) if base else None,
         "stage_ms": {"sort": ms_sort, "knn": ms_knn, "features": ms_feat, "mlp": ms_mlp, "clip": ms_clip,
                      "assemble": mean("ms_assemble"), "fallback": mean("ms_fallback")},
         "sort_gbs": SORT_BYTES_PER_POINT[P.dtype.type] * n / (ms_sort / 1e3) / 1e9,
@@ -192,6 +205,11 @@ def main(argv=None) -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if kmodel is not None:
+        out["kmodel"] = {"tau": kmodel.tau, "train_loss_per_epoch": [round(x, 5) for x in kmodel.history],
+                         "label_hist": getattr(kmodel, "label_hist", None),
+                         "train_s": round(getattr(kmodel, "train_seconds", 0.0), 2),
+                         "label_s": round(getattr(kmodel, "prep_seconds", 0.0), 2)}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -207,9 +225,23 @@ def cpu_baseline(P: np.ndarray) -> dict:
     t = time.perf_counter()
     oracle.tessellate(S, lo, hi, threads=threads)
     dt = time.perf_counter() - t
+    # one thread, on 2^15 seeded cells of the same sample
+    cells = np.sort(np.random.default_rng(0).choice(len(S), min(len(S), 1 << 15), replace=False))
+    t = time.perf_counter()
+    oracle.tessellate(S, lo, hi, threads=1, cells=cells)
+    dt1 = time.perf_counter() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": len(S) / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(S)} points of the workload inside [0,0.5)^3, tessellated in that sub-box "
-                      f"(FP64 C++ OpenMP oracle, {dt:.1f} s)"}
+                      f"(FP64 C++ OpenMP oracle, {dt:.1f} s)",
+            "one_thread": {"value": len(cells) / dt1, "unit": "cells/s",
+                           "sample": f"{len(cells)} seeded cells of the same sub-box ({dt1:.1f} s)"},
+            "cpu_model": model}
 
 
 if __name__ == "__main__":

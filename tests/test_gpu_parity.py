@@ -437,3 +437,81 @@ def test_clip_stream_phase(prec):
         i = pn[s]
         got = np.sort(pn[nbr[s, :cnt[s]]])
         assert np.array_equal(got, orc["col"][orc["row_ptr"][i]:orc["row_ptr"][i + 1]])
+
+
+# ------------------------------------------------------------ dataset reports
+
+_ORC_CACHE = {}
+
+
+def _oracle_full(name):
+    if name not in _ORC_CACHE:
+        P = gen.make(name, seed=0)
+        _ORC_CACHE[name] = (P, oracle.tessellate(P.astype(np.float64)))
+    return _ORC_CACHE[name]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_uniform_1m_every_cell(prec):
+    """2^20 uniform points (FP32 positions), k 32 -> 64 then the stream phase:
+    every neighbour set and every volume against the oracle."""
+    P, orc = _oracle_full("uniform-1m-f32")
+    res = vt.tessellate(torch.from_numpy(P).cuda(), k0=32, max_gpu_retries=1, precision=prec)
+    bad = compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
+    assert not bad, bad[:5]
+    viol, rel = volume_errors(res.volume.cpu().numpy(), orc["volume"], prec)
+    note(f"  uniform 1M {prec}: passes {res.stats['passes']} streamed {res.stats['streamed_cells']} "
+         f"max rel vol err {rel.max():.2e}")
+    assert not viol.any()
+    assert abs(res.volume.double().sum().item() - 1.0) <= (1e-10 if prec == "f64" else 1e-6)
+
+
+def test_cluster_4m_fp32_report():
+    """2^22 clustered points, FP32 clipping with FP64 rechecks (eps 1e-6), k 32
+    -> 64 then the stream phase: per-pass failures, recheck count, and the FP32
+    error against the oracle on 3000 seeded cells (volumes; vertices solved
+    from each vertex's three planes in long double)."""
+    P = gen.make("cluster-4m-f32", seed=0)
+    pts = torch.from_numpy(P).cuda()
+    res = vt.tessellate(pts, k0=32, max_gpu_retries=1, precision="f32")
+    st = res.stats
+    note(f"  cluster 4M f32: passes {st['passes']} streamed {st['streamed_cells']} capacity "
+         f"{st['capacity_cells']} host {st['fallback_cells']} rechecks {st['rechecks']} refined "
+         f"{st['refined_cells']} unresolved {st['unresolved_cells']}")
+    assert st["unresolved_cells"] == 0
+    rng = np.random.default_rng(7)
+    cells = np.sort(rng.choice(len(P), 3000, replace=False))
+    P64 = P.astype(np.float64)
+    orc = oracle.tessellate(P64, cells=cells)
+    viol, rel = volume_errors(res.volume.cpu().numpy(), orc["volume"], "f32", rows=cells)
+    note(f"  volume rel err p50 {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
+    assert not viol.any()
+    # vertices of the same cells from the clip call (sorted indices), FP32 path
+    cs, perm, srt, grid = vt.grid_sort(pts)
+    pn = perm.cpu().numpy()
+    inv = np.empty_like(pn)
+    inv[pn] = np.arange(len(pn))
+    q = torch.from_numpy(inv[cells].astype(np.int32)).cuda()
+    lists = vt.knn(srt, grid, cs, 64, queries=q, dist="f32")
+    r = vt.clip_cells(srt, lists, 64, cells=q, precision="f32", stream=True, grid=grid, cell_start=cs,
+                      max_vert=256, max_nbr=256)
+    stc = r["status"].cpu().numpy()
+    ok = np.nonzero(stc == 0)[0]
+    vc, vv, vp = r["vcount"].cpu().numpy(), r["verts"].cpu().numpy(), r["vplanes"].cpu().numpy()
+    rows, keys, got = [], [], []
+    for t in ok:
+        i = cells[t]
+        for m in range(vc[t]):
+            pl = vp[t, m]
+            rows.append(i)
+            keys.append([pn[x] if x >= 0 else x for x in pl])
+            got.append(vv[t, m])
+    rows, keys, got = np.array(rows), np.array(keys), np.array(got)
+    ref, kappa = triple_vertices(P64, rows, keys)
+    R = np.zeros(len(P))
+    np.maximum.at(R, rows, np.abs(ref - P64[rows]).max(1))
+    err = np.abs(got - ref).max(1) / R[rows]
+    note(f"  vertex err / R p50 {np.median(err):.2e} p99 {np.percentile(err, 99):.2e} max {err.max():.2e} "
+         f"({len(err)} vertices of {len(ok)} cells)")
+    assert len(ok) >= 0.99 * len(cells)
+    assert np.percentile(err, 99) <= 1e-6 and err.max() <= 16e-6 * (1 + 1e-3)
