@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 benchmark's CPU-baseline leg, never by the product library.  It shares no
 code with the HIP path.
 
-* :func:`tessellate` -- exact FP64 cells (volumes, neighbour lists, face
-  areas, vertices) from the C++ file ``voronoi_oracle.cpp``;
+* :func:`tessellate` -- exact FP64 cells (volumes, centroids, neighbour
+  lists, face areas, vertices) from the C++ file ``voronoi_oracle.cpp``;
 * :func:`kneeded`    -- the least neighbour-list size k at which the method
   certifies each cell, and the method's work at a given k;
 * ``oracle.mlp``     -- FP64 forward/backward of the k-bucket network;
@@ -53,6 +53,8 @@ def _load():
         lib.orc_nvert.restype = i64
         lib.orc_fetch.argtypes = [P] * 11
         lib.orc_fetch.restype = None
+        lib.orc_fetch_centroid.argtypes = [P, P]
+        lib.orc_fetch_centroid.restype = None
         lib.orc_free.argtypes = [P]
         lib.orc_free.restype = None
         lib.orc_kneeded.argtypes = [P, i64, P, P, P, i64, i64, i64, ctypes.c_int, P, P, P, P]
@@ -82,7 +84,8 @@ def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False,
 
     ``all_planes`` clips by every other point (no early stop) -- the check of
     the stopping lemma.  Returns a dict with ``row_ptr, col, area, volume,
-    work [n,4] (tested, cuts, evals, created), euler`` and, with ``vertices``,
+    centroid [n,3], work [n,4] (tested, cuts, evals, created), euler`` and,
+    with ``vertices``,
     ``vrow_ptr, vxyz [nv,3], vplanes [nv,3], vdeg``.
     """
     lib = _load()
@@ -101,7 +104,8 @@ def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False,
         nv = lib.orc_nvert(h)
         out = dict(row_ptr=np.zeros(n + 1, np.int64), col=np.zeros(nnz, np.int32),
                    area=np.zeros(nnz, np.float64), volume=np.zeros(n, np.float64),
-                   work=np.zeros((n, 4), np.int64), euler=np.zeros(n, np.int32))
+                   work=np.zeros((n, 4), np.int64), euler=np.zeros(n, np.int32),
+                   centroid=np.zeros((n, 3), np.float64))
         if vertices:
             out.update(vrow_ptr=np.zeros(n + 1, np.int64), vxyz=np.zeros((nv, 3), np.float64),
                        vplanes=np.zeros((nv, 3), np.int32), vdeg=np.zeros(nv, np.int32))
@@ -109,6 +113,7 @@ def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False,
         lib.orc_fetch(h, _ptr(out["row_ptr"]), _ptr(out["col"]), _ptr(out["area"]), _ptr(out["volume"]),
                       _ptr(out["work"]), _ptr(out["euler"]), _ptr(g("vrow_ptr")), _ptr(g("vxyz")),
                       _ptr(g("vplanes")), _ptr(g("vdeg")))
+        lib.orc_fetch_centroid(h, _ptr(out["centroid"]))
     finally:
         lib.orc_free(h)
     return out

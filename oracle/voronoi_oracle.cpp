@@ -166,6 +166,22 @@ struct Poly {
     return vol / 6.0;
   }
 
+  // First moment about the seed.  The same fan tetrahedra as volume(): the
+  // centroid of a tetrahedron is the mean of its four corners, and one
+  // corner is the seed (the origin here).
+  V3 moment() const {
+    V3 m = {0, 0, 0};
+    for (const auto& cyc : f)
+      for (size_t i = 1; i + 1 < cyc.size(); ++i) {
+        const V3& a = v[cyc[0]];
+        const V3& b = v[cyc[i]];
+        const V3& c = v[cyc[i + 1]];
+        const double w = dot3(a, cross3(b, c)) / 24.0;  // volume / 4
+        for (int k = 0; k < 3; ++k) m[k] += w * (a[k] + b[k] + c[k]);
+      }
+    return m;
+  }
+
   double face_area(size_t k) const {
     const auto& cyc = f[k];
     V3 a = {0, 0, 0};
@@ -363,6 +379,7 @@ struct Result {
   std::vector<int32_t> col;
   std::vector<double> area;  // face area per (row, col) entry
   std::vector<double> vol;
+  std::vector<double> cen;   // [n,3] cell centroids (absolute)
   std::vector<int64_t> vrow_ptr;
   std::vector<double> vxyz;
   std::vector<int32_t> vplanes;  // three smallest incident plane ids
@@ -395,6 +412,7 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
   Result* res = new Result;
   res->n = n;
   res->vol.assign(n, 0.0);
+  res->cen.assign(3 * n, 0.0);
   res->work.assign(4 * n, 0);
   res->euler.assign(n, 0);
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -407,6 +425,8 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
     Work w;
     exact_cell(G, P, n, lo, hi, i, all, C, w);
     res->vol[i] = C.volume();
+    const V3 mom = C.moment();
+    for (int a = 0; a < 3; ++a) res->cen[3 * i + a] = P[3 * i + a] + (res->vol[i] > 0.0 ? mom[a] / res->vol[i] : 0.0);
     res->work[4 * i + 0] = w.tested;
     res->work[4 * i + 1] = w.cuts;
     res->work[4 * i + 2] = w.evals;
@@ -477,6 +497,11 @@ void orc_fetch(const orc_result* r, int64_t* row_ptr, int32_t* col, double* area
   cp(vxyz, r->vxyz.data(), r->vxyz.size() * sizeof(double));
   cp(vplanes, r->vplanes.data(), r->vplanes.size() * sizeof(int32_t));
   cp(vdeg, r->vdeg.data(), r->vdeg.size() * sizeof(int32_t));
+}
+
+// Cell centroids [n,3] (zero for rows not computed).
+void orc_fetch_centroid(const orc_result* r, double* cen) {
+  if (cen && !r->cen.empty()) std::memcpy(cen, r->cen.data(), r->cen.size() * sizeof(double));
 }
 
 void orc_free(orc_result* r) { delete r; }

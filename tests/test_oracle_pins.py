@@ -5,9 +5,11 @@ pinned by: brute force on tiny inputs (every plane triple, no clipping); the
 stopping lemma (the certified cell equals the cell clipped by all N-1
 bisectors); an independent half-space intersection (scipy's Qhull) on medium
 inputs; closed forms (one point, a slab split, BCC and simple-cubic lattices,
-the 8 octant centres); invariants (volumes tile the box, symmetric neighbour
-relation, Euler's formula, equidistant vertices, empty spheres, equal face
-areas seen from both sides); and the Poisson-Voronoi mean face count.
+the 8 octant centres, with their centroids and face areas); invariants
+(volumes tile the box, first moments add up to the box's, pyramids over the
+faces of interior cells fill the cell, symmetric neighbour relation, Euler's
+formula, equidistant vertices, empty spheres, equal face areas seen from both
+sides); and the Poisson-Voronoi mean face count.
 """
 import json
 import os
@@ -38,9 +40,12 @@ def test_oracle_matches_brute_force(seed):
         P = rng.random((n, 3))
     lo, hi = ((0, 0, 0), (1, 1, 1)) if seed % 4 else ((-0.1, 0.0, -0.3), (1.2, 1.0, 1.05))
     r = oracle.tessellate(P, lo, hi, vertices=True)
-    vol, nbrs, verts = brute.brute_cells(P, lo, hi)
+    vol, nbrs, verts, areas, cents = brute.brute_cells(P, lo, hi, geometry=True)
     np.testing.assert_allclose(r["volume"], vol, rtol=0, atol=1e-13)
     assert _rows(r) == nbrs
+    want_area = np.array([areas[i][j] for i in range(len(P)) for j in nbrs[i]])
+    np.testing.assert_allclose(r["area"], want_area, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["centroid"], cents, rtol=0, atol=1e-11)
     for i in range(len(P)):
         a, b = r["vrow_ptr"][i], r["vrow_ptr"][i + 1]
         got = {tuple(int(x) for x in r["vplanes"][k]): r["vxyz"][k] for k in range(a, b)}
@@ -103,6 +108,9 @@ def test_closed_forms():
         r = oracle.tessellate(P, lo, hi)
         np.testing.assert_allclose(r["volume"], case["volume"], rtol=1e-13, atol=1e-15, err_msg=case["name"])
         assert _rows(r) == case["neighbours"], case["name"]
+        np.testing.assert_allclose(r["centroid"], case["centroid"], rtol=1e-13, atol=1e-15, err_msg=case["name"])
+        want = np.array([a for row in case["area"] for a in row], dtype=np.float64)
+        np.testing.assert_allclose(r["area"], want, rtol=1e-13, atol=1e-15, err_msg=case["name"])
 
 
 def _lattice_bcc(m):
@@ -132,6 +140,15 @@ def test_bcc_truncated_octahedra():
     vr = np.diff(r["vrow_ptr"])
     assert np.all(vr[interior] == 24)
     assert abs(r["volume"].sum() - 1.0) < 1e-12
+    # centrally symmetric cells: centroid = generator; 8 regular hexagons of
+    # edge a sqrt(2)/4 towards the body-diagonal neighbours (3 sqrt(3) a^2/16)
+    # and 6 squares of that edge towards the axis neighbours (a^2/8)
+    np.testing.assert_allclose(r["centroid"][interior], P[interior], rtol=0, atol=1e-14)
+    for i in np.nonzero(interior)[0]:
+        a0, a1 = r["row_ptr"][i], r["row_ptr"][i + 1]
+        d = np.linalg.norm(P[r["col"][a0:a1]] - P[i], axis=1)
+        want = np.where(d < 0.9 * a, 3 * np.sqrt(3) * a * a / 16, a * a / 8)
+        np.testing.assert_allclose(r["area"][a0:a1], want, rtol=1e-12)
 
 
 def test_simple_cubic_lattice():
@@ -143,6 +160,9 @@ def test_simple_cubic_lattice():
     idx = np.rint(P * m - 0.5).astype(int)
     expect = 6 - np.sum((idx == 0) | (idx == m - 1), axis=1)
     assert np.array_equal(np.diff(r["row_ptr"]), expect)
+    # every cell is the cube around its generator: centroid = generator, faces 1/m^2
+    np.testing.assert_allclose(r["centroid"], P, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(r["area"], 1.0 / m ** 2, rtol=1e-13)
 
 
 def _invariants(P, r, tol_rel=1e-12):
@@ -160,6 +180,20 @@ def _invariants(P, r, tol_rel=1e-12):
         assert (j, i) in area, (i, j)
         # relative, floored at 1e-12 of the mean face scale (tiny cluster faces)
         assert abs(area[(j, i)] - a) <= 1e-10 * a + 1e-12 * (1.0 / n) ** (2 / 3)
+    # centroids: the first moments of the cells add up to the box's (centre 1/2)
+    mom = (r["volume"][:, None] * r["centroid"]).sum(0)
+    np.testing.assert_allclose(mom, 0.5, rtol=0, atol=1e-12)
+    # areas: a cell with no box-wall face is the union of the pyramids from its
+    # generator over its faces, of height |p_j - p_i| / 2
+    walls = np.zeros(n, bool)
+    owner = np.repeat(np.arange(n), np.diff(r["vrow_ptr"]))
+    np.logical_or.at(walls, owner, np.any(r["vplanes"] < 0, axis=1))
+    own = np.repeat(np.arange(n), np.diff(r["row_ptr"]))
+    h = np.linalg.norm(P[r["col"]] - P[own], axis=1) / 2
+    pyr = np.bincount(own, weights=r["area"] * h / 3, minlength=n)
+    inner = ~walls
+    assert inner.sum() > n // 2
+    np.testing.assert_allclose(pyr[inner], r["volume"][inner], rtol=1e-11)
     # closed convex polyhedra
     assert np.all(r["euler"] == 2)
     # generic vertices: three faces; equidistant from the generators of their faces
