@@ -200,12 +200,18 @@ typedef struct {
  *              (valid where status == CERTIFIED)
  *   vcount     [rows] int32, verts [rows,max_vert,3] double (absolute),
  *   vplanes    [rows,max_vert,3] int32 (sorted indices or -1..-6)   (nullable)
+ *   area       [rows,max_nbr] double out (nullable): area of the face shared
+ *              with nbr[row, e], at the same position
+ *   centroid   [rows,3] double out (nullable): cell centroid (absolute)
+ * Face areas and centroids are computed in double from double vertices
+ * (solved from the exact inputs on the F32_RECHECK path).  Every output of a
+ * row that is not CERTIFIED is 0 (counts) or left unwritten (lists).
  * rows = n when out_by_id, else nc. */
 VOTESS_API votess_status votess_clip_cells(votess_ctx* ctx, const void* sorted, votess_dtype dtype, int64_t n,
                                 const votess_box* box, const int32_t* cells, int64_t nc, const int32_t* knn,
                                 int32_t k, const votess_clip_opts* opts, uint8_t* status, int32_t* nbr_count,
                                 int32_t* nbr, double* volume, int32_t* kneeded, int32_t* vcount, double* verts,
-                                int32_t* vplanes, void* stream);
+                                int32_t* vplanes, double* area, double* centroid, void* stream);
 
 /* ------------------------------------------------------ whole tessellation */
 
@@ -228,6 +234,7 @@ typedef struct {
   int32_t gpu_stream;       /* 1 (default): the last GPU pass keeps clipping uncertified
                                cells by grid rings (no bound on k) instead of leaving
                                them to the host */
+  int32_t want_faces;       /* 1: also return face areas and cell centroids */
 } votess_params;
 
 #define VOTESS_MAX_PASSES 8
@@ -255,6 +262,8 @@ typedef struct {
   int64_t* vrow_ptr; /* [n+1] device (want_vertices) */
   double* vxyz;      /* [nvert,3] device */
   int32_t* vplanes;  /* [nvert,3] device: sorted plane ids per vertex */
+  double* area;      /* [nnz] device (want_faces): area of the face shared with col[e] */
+  double* centroid;  /* [n,3] device (want_faces): cell centroids */
   votess_stats stats;
 } votess_result;
 

@@ -182,11 +182,12 @@ def knn(sorted_: torch.Tensor, grid: _lib.Grid, cell_start: torch.Tensor, k: int
 def clip_cells(sorted_: torch.Tensor, knn_: torch.Tensor, k: int, box=((0, 0, 0), (1, 1, 1)), cells=None,
                precision: str = "f64", eps: float = 1e-6, knn_dist: str | None = None, max_nbr: int = 64,
                max_vert: int = 0, capacity: int = 0, kneeded: bool = True, stream: bool = False, grid=None,
-               cell_start=None, ctx: Context | None = None) -> dict:
+               cell_start=None, faces: bool = False, ctx: Context | None = None) -> dict:
     """Clips each cell by its k-list; per-cell status, neighbours, volume.
 
     With ``stream`` (needs ``grid`` and ``cell_start``), a cell its list does
-    not certify keeps clipping by grid rings until certified."""
+    not certify keeps clipping by grid rings until certified.  With ``faces``,
+    also ``area`` [rows, max_nbr] (next to ``nbr``) and ``centroid`` [rows, 3]."""
     ctx = ctx or Context.get()
     n = sorted_.shape[0]
     nc = n if cells is None else cells.shape[0]
@@ -202,6 +203,9 @@ def clip_cells(sorted_: torch.Tensor, knn_: torch.Tensor, k: int, box=((0, 0, 0)
         out["vcount"] = torch.empty(rows, dtype=torch.int32, device=dev)
         out["verts"] = torch.empty(rows, max_vert, 3, dtype=torch.float64, device=dev)
         out["vplanes"] = torch.empty(rows, max_vert, 3, dtype=torch.int32, device=dev)
+    if faces:
+        out["area"] = torch.empty(rows, max_nbr, dtype=torch.float64, device=dev)
+        out["centroid"] = torch.empty(rows, 3, dtype=torch.float64, device=dev)
     o = _lib.ClipOpts()
     o.precision = _PREC[precision]
     o.eps = eps
@@ -223,7 +227,7 @@ def clip_cells(sorted_: torch.Tensor, knn_: torch.Tensor, k: int, box=((0, 0, 0)
                                     _ptr(knn_), int(k), C.byref(o), _ptr(out["status"]), _ptr(out["nbr_count"]),
                                     _ptr(out["nbr"]), _ptr(out["volume"]), _ptr(out.get("kneeded")),
                                     _ptr(out.get("vcount")), _ptr(out.get("verts")), _ptr(out.get("vplanes")),
-                                    _stream()))
+                                    _ptr(out.get("area")), _ptr(out.get("centroid")), _stream()))
     return {key: v[:nc] for key, v in out.items()}
 
 
@@ -237,6 +241,8 @@ class Result:
     vrow_ptr: torch.Tensor | None = None
     vxyz: torch.Tensor | None = None
     vplanes: torch.Tensor | None = None
+    area: torch.Tensor | None = None      # [nnz] float64: face shared with col[e] (faces=True)
+    centroid: torch.Tensor | None = None  # [n,3] float64 (faces=True)
     stats: dict = field(default_factory=dict)
 
     def neighbours(self, i: int) -> torch.Tensor:
@@ -246,9 +252,12 @@ class Result:
 def tessellate(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), k0: int = 32, max_gpu_retries: int = 1,
                precision: str = "f64", eps: float = 1e-6, pts_per_cell: float = 2.0, kmodel=None, tau: float = 0.9,
                vertices: bool = False, index_space: str = "original", host_fallback: bool = True,
-               host_threads: int = 0, force_fail_every: int = 0, gpu_stream: bool = True,
+               host_threads: int = 0, force_fail_every: int = 0, gpu_stream: bool = True, faces: bool = False,
                ctx: Context | None = None) -> Result:
-    """Voronoi cells of ``points`` [n,3] (cuda, float32/float64) clipped to ``box``."""
+    """Voronoi cells of ``points`` [n,3] (cuda, float32/float64) clipped to ``box``.
+
+    With ``faces``, also the area of every neighbour's face (``area``, next to
+    ``col``) and the cell centroids (``centroid``)."""
     ctx = ctx or Context.get(points.device.index)
     pts = points.contiguous()
     p = _lib.Params()
@@ -266,6 +275,7 @@ def tessellate(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), k0: int = 32, m
     p.host_threads = host_threads
     p.force_fail_every = force_fail_every
     p.gpu_stream = int(bool(gpu_stream))
+    p.want_faces = int(bool(faces))
     r = _lib.Result()
     b = _box(box)
     n = pts.shape[0]
@@ -279,4 +289,7 @@ def tessellate(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), k0: int = 32, m
         out.vrow_ptr = ctx.take(r.vrow_ptr, torch.int64, (n + 1,))
         out.vxyz = ctx.take(r.vxyz, torch.float64, (max(r.nvert, 1), 3))[: r.nvert]
         out.vplanes = ctx.take(r.vplanes, torch.int32, (max(r.nvert, 1), 3))[: r.nvert]
+    if faces:
+        out.area = ctx.take(r.area, torch.float64, (max(r.nnz, 1),))[: r.nnz]
+        out.centroid = ctx.take(r.centroid, torch.float64, (max(n, 1), 3))[:n]
     return out

@@ -38,7 +38,8 @@ class Params(C.Structure):
     _fields_ = [("k0", C.c_int32), ("max_gpu_retries", C.c_int32), ("pts_per_cell", C.c_double),
                 ("precision", C.c_int), ("eps", C.c_double), ("kmodel", C.c_void_p), ("tau", C.c_double),
                 ("want_vertices", C.c_int32), ("index_space", C.c_int32), ("host_fallback", C.c_int32),
-                ("host_threads", C.c_int32), ("force_fail_every", C.c_int32), ("gpu_stream", C.c_int32)]
+                ("host_threads", C.c_int32), ("force_fail_every", C.c_int32), ("gpu_stream", C.c_int32),
+                ("want_faces", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -65,7 +66,7 @@ class Stats(C.Structure):
 class Result(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
                 ("volume", C.c_void_p), ("nvert", C.c_int64), ("vrow_ptr", C.c_void_p), ("vxyz", C.c_void_p),
-                ("vplanes", C.c_void_p), ("stats", Stats)]
+                ("vplanes", C.c_void_p), ("area", C.c_void_p), ("centroid", C.c_void_p), ("stats", Stats)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -88,7 +89,7 @@ SIGNATURES = {
     "votess_sub_capacity": (i64, [i64]),
     "votess_knn": (C.c_int, [P, P, C.c_int, i64, C.POINTER(Grid), P, P, P, P, i64, i32, C.c_int, P, P]),
     "votess_clip_cells": (C.c_int, [P, P, C.c_int, i64, C.POINTER(Box), P, i64, P, i32, C.POINTER(ClipOpts),
-                                    P, P, P, P, P, P, P, P, P]),
+                                    P, P, P, P, P, P, P, P, P, P, P]),
     "votess_params_default": (None, [C.POINTER(Params)]),
     "votess_tessellate": (C.c_int, [P, P, C.c_int, i64, C.POINTER(Box), C.POINTER(Params), C.POINTER(Result), P]),
     "votess_result_free": (None, [P, C.POINTER(Result)]),

@@ -271,7 +271,7 @@ votess_status votess_clip_cells(votess_ctx* ctx, const void* sorted, votess_dtyp
                                 const votess_box* box, const int32_t* cells, int64_t nc, const int32_t* knn,
                                 int32_t k, const votess_clip_opts* opts, uint8_t* status, int32_t* nbr_count,
                                 int32_t* nbr, double* volume, int32_t* kneeded, int32_t* vcount, double* verts,
-                                int32_t* vplanes, void* stream) {
+                                int32_t* vplanes, double* area, double* centroid, void* stream) {
   if (!ctx || !opts) return fail(VOTESS_EINVAL, "clip: null ctx/opts");
   VT_TRY(check_box(box));
   if (!cells) nc = n;
@@ -311,6 +311,8 @@ votess_status votess_clip_cells(votess_ctx* ctx, const void* sorted, votess_dtyp
   a.vcount = vcount;
   a.verts = verts;
   a.vplanes = vplanes;
+  a.area = area;
+  a.centroid = centroid;
   a.counters = nullptr;
   a.stream = opts->stream;
   if (opts->stream) {
@@ -351,6 +353,10 @@ void votess_result_free(votess_ctx* ctx, votess_result* r) {
   dev_free(ctx, r->vrow_ptr);
   dev_free(ctx, r->vxyz);
   dev_free(ctx, r->vplanes);
+  dev_free(ctx, r->area);
+  dev_free(ctx, r->centroid);
+  r->area = nullptr;
+  r->centroid = nullptr;
   r->row_ptr = nullptr;
   r->col = nullptr;
   r->volume = nullptr;
@@ -408,10 +414,11 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   VT_TRY(votess_grid_plan(n, box, P.pts_per_cell, &grid));
   const size_t esz = dtype == VOTESS_F32 ? 4 : 8;
   const bool wantv = P.want_vertices != 0;
+  const bool wantf = P.want_faces != 0;
   const votess_dtype dist = P.precision == VOTESS_CLIP_F32_RECHECK ? VOTESS_F32 : VOTESS_F64;
 
   Buf cell_start, perm, sorted, status, nbr_count, nbr, vol, vcount, verts, vplanes, knn, cells, cells2, counters;
-  Buf subinfo, sub_start;
+  Buf subinfo, sub_start, farea, fcen;
   const size_t nn = (size_t)std::max(n, 1);
   VT_TRY(alloc_buf(ctx, cell_start, (grid.ncells + 1) * 4));
   VT_TRY(alloc_buf(ctx, subinfo, grid.ncells * 8));
@@ -429,6 +436,10 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     VT_TRY(alloc_buf(ctx, vcount, nn * 4));
     VT_TRY(alloc_buf(ctx, verts, nn * kMaxVert * 3 * 8));
     VT_TRY(alloc_buf(ctx, vplanes, nn * kMaxVert * 3 * 4));
+  }
+  if (wantf) {
+    VT_TRY(alloc_buf(ctx, farea, nn * kMaxNbr * 8));
+    VT_TRY(alloc_buf(ctx, fcen, nn * 3 * 8));
   }
   VT_TRY(ctx->ws.reserve(std::max(grid_sort_workspace(n, grid.ncells), scan_workspace(n) + nn * 4 + 4096)));
   VT_HIP(hipMemsetAsync(ctx->d_err, 0, 4, st));
@@ -467,6 +478,8 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   base.vcount = wantv ? vcount.get<int32_t>() : nullptr;
   base.verts = wantv ? verts.get<double>() : nullptr;
   base.vplanes = wantv ? vplanes.get<int32_t>() : nullptr;
+  base.area = wantf ? farea.get<double>() : nullptr;
+  base.centroid = wantf ? fcen.get<double>() : nullptr;
   base.counters = counters.get<unsigned long long>();
   const GridDev GD = to_dev(grid);
   base.grid = GD;
@@ -613,10 +626,15 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     VT_HIP(hipStreamSynchronize(st));
     std::sort(ids.begin(), ids.end());
     std::vector<HostCellOut> res;
-    host_fallback_cells(rec.data(), dtype, n, grid, cs.data(), ids.data(), nhost, wantv, P.host_threads, res);
+    host_fallback_cells(rec.data(), dtype, n, grid, cs.data(), ids.data(), nhost, wantv, wantf, P.host_threads,
+                        res);
     // write back per cell (small transfers, batched through host staging)
     std::vector<int32_t> h_cnt(nhost), h_nbr((size_t)nhost * kMaxNbr, -1), h_vc;
-    std::vector<double> h_vol(nhost), h_v;
+    std::vector<double> h_vol(nhost), h_v, h_area, h_cen;
+    if (wantf) {
+      h_area.assign((size_t)nhost * kMaxNbr, 0.0);
+      h_cen.assign((size_t)nhost * 3, 0.0);
+    }
     std::vector<int32_t> h_vp;
     std::vector<uint8_t> h_st(nhost);
     if (wantv) {
@@ -632,6 +650,10 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
       std::copy(o.nbr.begin(), o.nbr.end(), h_nbr.begin() + (size_t)i * kMaxNbr);
       h_vol[i] = o.volume;
       h_st[i] = VOTESS_CELL_CERTIFIED;
+      if (wantf) {
+        std::copy(o.area.begin(), o.area.end(), h_area.begin() + (size_t)i * kMaxNbr);
+        std::copy(o.centroid, o.centroid + 3, h_cen.begin() + (size_t)i * 3);
+      }
       if (wantv) {
         const int nv = (int)o.vplanes.size() / 3;
         if (nv > kMaxVert) return fail(VOTESS_ECAPACITY, "cell %d has %d vertices", ids[i], nv);
@@ -649,6 +671,12 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
                             (size_t)len * kMaxNbr * 4, hipMemcpyHostToDevice, st));
       VT_HIP(hipMemcpyAsync(vol.get<double>() + s0, &h_vol[i], len * 8, hipMemcpyHostToDevice, st));
       VT_HIP(hipMemcpyAsync(status.get<uint8_t>() + s0, &h_st[i], len, hipMemcpyHostToDevice, st));
+      if (wantf) {
+        VT_HIP(hipMemcpyAsync(farea.get<double>() + (size_t)s0 * kMaxNbr, &h_area[(size_t)i * kMaxNbr],
+                              (size_t)len * kMaxNbr * 8, hipMemcpyHostToDevice, st));
+        VT_HIP(hipMemcpyAsync(fcen.get<double>() + (size_t)s0 * 3, &h_cen[(size_t)i * 3], (size_t)len * 3 * 8,
+                              hipMemcpyHostToDevice, st));
+      }
       if (wantv) {
         VT_HIP(hipMemcpyAsync(vcount.get<int32_t>() + s0, &h_vc[i], len * 4, hipMemcpyHostToDevice, st));
         VT_HIP(hipMemcpyAsync(verts.get<double>() + (size_t)s0 * kMaxVert * 3, &h_v[(size_t)i * kMaxVert * 3],
@@ -666,17 +694,23 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   // ---- a9 assembly
   {
     Timer T(st, &S.ms_assemble);
-    Buf row_ptr, col, volume;
+    Buf row_ptr, col, volume, area, centroid;
     VT_TRY(alloc_buf(ctx, row_ptr, (nn + 1) * 8));
     VT_TRY(alloc_buf(ctx, volume, nn * 8));
     int64_t nnz = 0;
-    VT_TRY(launch_assemble(nbr_count.get<int32_t>(), nbr.get<int32_t>(), kMaxNbr, vol.get<double>(),
-                           perm.get<int32_t>(), n, P.index_space, row_ptr.get<int64_t>(), nullptr, nullptr, ctx->ws,
-                           st, &nnz));
+    VT_TRY(launch_assemble(nbr_count.get<int32_t>(), nbr.get<int32_t>(), kMaxNbr, vol.get<double>(), nullptr, nullptr,
+                           perm.get<int32_t>(), n, P.index_space, row_ptr.get<int64_t>(), nullptr, nullptr, nullptr,
+                           nullptr, ctx->ws, st, &nnz));
     VT_TRY(alloc_buf(ctx, col, (size_t)std::max<int64_t>(nnz, 1) * 4));
+    if (wantf) {
+      VT_TRY(alloc_buf(ctx, area, (size_t)std::max<int64_t>(nnz, 1) * 8));
+      VT_TRY(alloc_buf(ctx, centroid, nn * 3 * 8));
+    }
     VT_TRY(launch_assemble(nbr_count.get<int32_t>(), nbr.get<int32_t>(), kMaxNbr, vol.get<double>(),
+                           wantf ? farea.get<double>() : nullptr, wantf ? fcen.get<double>() : nullptr,
                            perm.get<int32_t>(), n, P.index_space, row_ptr.get<int64_t>(), col.get<int32_t>(),
-                           volume.get<double>(), ctx->ws, st, &nnz));
+                           volume.get<double>(), wantf ? area.get<double>() : nullptr,
+                           wantf ? centroid.get<double>() : nullptr, ctx->ws, st, &nnz));
     out->n = n;
     out->nnz = nnz;
     if (wantv) {
@@ -700,6 +734,10 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     out->row_ptr = (int64_t*)row_ptr.release();
     out->col = (int32_t*)col.release();
     out->volume = (double*)volume.release();
+    if (wantf) {
+      out->area = (double*)area.release();
+      out->centroid = (double*)centroid.release();
+    }
   }
   S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   return VOTESS_OK;

@@ -1,7 +1,8 @@
 // Retry compaction (cells whose certificate failed) and output assembly: the
 // per-cell neighbour lists become one CSR "jagged array" of neighbour indices
 // (paper, Features section), rows in original input order by default or in
-// grid-sorted order, each row ascending; volumes and vertices follow.
+// grid-sorted order, each row ascending; volumes, face areas, centroids and
+// vertices follow.
 #include "internal.h"
 
 namespace votess {
@@ -35,25 +36,36 @@ __global__ void k_rows_count(const int* __restrict__ nbr_count, const int* __res
   counts[sorted_space ? s : perm[s]] = nbr_count[s];
 }
 
-__global__ void k_rows_fill(const int* __restrict__ nbr_count, const int* __restrict__ nbr, int max_nbr,
-                            const int* __restrict__ perm, const double* __restrict__ vol_sorted, int n,
-                            int sorted_space, const long long* __restrict__ row_ptr, int* __restrict__ col,
-                            double* __restrict__ volume) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// One thread per row: the row's neighbour ids (mapped to the output index
+// space) are staged in LDS, column-major so that the block's threads hit
+// distinct banks, and each id goes straight to its rank in the row (ids of a
+// row are distinct), so every output is written once.  Areas move with their
+// ids; centroids with their rows.
+constexpr int kFillBlock = 64;
+template <int MAXN>
+__global__ __launch_bounds__(kFillBlock) void k_rows_fill(
+    const int* __restrict__ nbr_count, const int* __restrict__ nbr, int max_nbr, const int* __restrict__ perm,
+    const double* __restrict__ vol_sorted, const double* __restrict__ area_sorted,
+    const double* __restrict__ cen_sorted, int n, int sorted_space, const long long* __restrict__ row_ptr,
+    int* __restrict__ col, double* __restrict__ volume, double* __restrict__ area, double* __restrict__ centroid) {
+  __shared__ int ids[MAXN * kFillBlock];
+  const int tid = threadIdx.x;
+  const int s = blockIdx.x * kFillBlock + tid;
   if (s >= n) return;
   const int r = sorted_space ? s : perm[s];
   volume[r] = vol_sorted[s];
-  const int cnt = nbr_count[s];
-  int* dst = col + row_ptr[r];
+  if (centroid)
+    for (int a = 0; a < 3; ++a) centroid[(size_t)r * 3 + a] = cen_sorted[(size_t)s * 3 + a];
+  const int cnt = min(nbr_count[s], max_nbr);
   const int* src = nbr + (size_t)s * max_nbr;
-  for (int e = 0; e < cnt; ++e) {  // insertion sort straight into the row
-    const int v = sorted_space ? src[e] : perm[src[e]];
-    int i = e;
-    while (i > 0 && dst[i - 1] > v) {
-      dst[i] = dst[i - 1];
-      --i;
-    }
-    dst[i] = v;
+  for (int e = 0; e < cnt; ++e) ids[e * kFillBlock + tid] = sorted_space ? src[e] : perm[src[e]];
+  const long long o = row_ptr[r];
+  for (int e = 0; e < cnt; ++e) {
+    const int v = ids[e * kFillBlock + tid];
+    int rank = 0;
+    for (int x = 0; x < cnt; ++x) rank += ids[x * kFillBlock + tid] < v;
+    col[o + rank] = v;
+    if (area) area[o + rank] = area_sorted[(size_t)s * max_nbr + e];
   }
 }
 
@@ -95,8 +107,9 @@ votess_status launch_compact_failed(const uint8_t* status, const int32_t* cells,
 }
 
 votess_status launch_assemble(const int32_t* nbr_count, const int32_t* nbr, int max_nbr, const double* vol_sorted,
-                              const int32_t* perm, int n, int index_space, int64_t* row_ptr, int32_t* col,
-                              double* volume, Workspace& ws, hipStream_t st, int64_t* nnz_h) {
+                              const double* area_sorted, const double* cen_sorted, const int32_t* perm, int n,
+                              int index_space, int64_t* row_ptr, int32_t* col, double* volume, double* area,
+                              double* centroid, Workspace& ws, hipStream_t st, int64_t* nnz_h) {
   const unsigned b = (unsigned)((n + 255) / 256);
   if (col == nullptr) {  // phase 1: counts -> row_ptr, nnz to the host
     const size_t mark = ws.used;
@@ -111,9 +124,12 @@ votess_status launch_assemble(const int32_t* nbr_count, const int32_t* nbr, int 
     ws.used = mark;
     return VOTESS_OK;
   }
+  if (max_nbr > 64) return fail(VOTESS_EINVAL, "assemble: rows longer than 64");
+  if ((area && !area_sorted) || (centroid && !cen_sorted)) return fail(VOTESS_EINVAL, "assemble: null face input");
   if (n > 0) {  // phase 2: fill
-    k_rows_fill<<<b, 256, 0, st>>>(nbr_count, nbr, max_nbr, perm, vol_sorted, n, index_space,
-                                   (const long long*)row_ptr, col, volume);
+    k_rows_fill<64><<<(unsigned)((n + kFillBlock - 1) / kFillBlock), kFillBlock, 0, st>>>(
+        nbr_count, nbr, max_nbr, perm, vol_sorted, area_sorted, cen_sorted, n, index_space,
+        (const long long*)row_ptr, col, volume, area, centroid);
     VT_HIP(hipGetLastError());
   }
   return VOTESS_OK;

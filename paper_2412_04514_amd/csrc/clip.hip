@@ -26,6 +26,10 @@
 //    with F_f the foot of the seed on face f and e_fg the point of line f^g
 //    nearest to the seed (a fan of each face from its foot, split at the edge
 //    anchors), accumulated in double.
+//  * Optional per-face outputs, in double from double vertices: the area of
+//    each neighbour's face (the same corner terms, per face) and the cell
+//    centroid (each corner term split into two signed tetrahedra from the
+//    seed, weighted by their corner means).
 //  * F32_RECHECK: tests and radii in float; a plane-side test whose margin is
 //    below eps of its scale, and a certificate comparison with
 //    |d^2 - 4 R^2| <= eps d^2, are redone in double from the exact inputs.
@@ -59,6 +63,8 @@ struct ClipArgs {
   int* vcount;
   double* verts;
   int* vplanes;
+  double* area;      // [rows, max_nbr] next to nbr (nullable)
+  double* centroid;  // [rows, 3] (nullable)
   unsigned long long* counters;
   // stream phase (cells the list did not certify keep clipping by grid rings)
   int stream;
@@ -89,6 +95,41 @@ __device__ __forceinline__ V3<R> solve3(const V3<R>& na, R ca, const V3<R>& nb, 
   const R inv = R(1) / det;
   return {(ca * bc.x + cb * ca_.x + cc * ab.x) * inv, (ca * bc.y + cb * ca_.y + cc * ab.y) * inv,
           (ca * bc.z + cb * ca_.z + cc * ab.z) * inv};
+}
+
+// c - n.v as if in twice the working precision: each product split exactly
+// by an FMA, each sum by an error-free two-sum, the error terms added last.
+// The residual of a vertex of nearly singular planes survives cancellation.
+__device__ __forceinline__ double residual2(const V3<double>& n, double c, const V3<double>& v) {
+#pragma clang fp contract(off)
+  double s = c, err = 0.0;
+  const double a[3] = {n.x, n.y, n.z}, b[3] = {v.x, v.y, v.z};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double p = a[i] * b[i];
+    const double ep = fma(a[i], b[i], -p);  // a b = p + ep exactly
+    const double t = s - p;                 // s - p = t + es exactly
+    const double z = t - s;
+    const double es = (s - (t - z)) + (-p - z);
+    s = t;
+    err += es - ep;
+  }
+  return s + err;
+}
+
+// Vertex of three planes, refined once against its accurate residual: a
+// few ulps of |v| unless the normals are singular to within ~u.
+__device__ __forceinline__ V3<double> solve3_refined(const V3<double>& na, double ca, const V3<double>& nb,
+                                                     double cb, const V3<double>& nc, double cc) {
+  const V3<double> bc = cross(nb, nc), ca_ = cross(nc, na), ab = cross(na, nb);
+  const double inv = 1.0 / dot(na, bc);
+  auto apply = [&](double x, double y, double z) -> V3<double> {
+    return {(x * bc.x + y * ca_.x + z * ab.x) * inv, (x * bc.y + y * ca_.y + z * ab.y) * inv,
+            (x * bc.z + y * ca_.z + z * ab.z) * inv};
+  };
+  const V3<double> v = apply(ca, cb, cc);
+  const V3<double> d = apply(residual2(na, ca, v), residual2(nb, cb, v), residual2(nc, cc, v));
+  return {v.x + d.x, v.y + d.y, v.z + d.z};
 }
 
 // Float vertex of three planes with a first-order forward error bound (max
@@ -987,11 +1028,46 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
   const bool cert = have && st == VOTESS_CELL_CERTIFIED;
   // volume: corner terms in double.  `exact` takes vertices and planes in
   // double from the inputs (float path, ill-conditioned cells only).
+  // Anchor of edge f^g: the point of the line nearest the seed,
+  // (c_f (n_g x d) - c_g (n_f x d)) / |d|^2 with d = n_f x n_g.  Its error
+  // grows like 1/sin of the angle between the planes; a solve of the 2x2 Gram
+  // system would square that, which shows on the faces of nearly parallel
+  // neighbours.
   auto anchor = [&](const V3<double>& nf, double cf, const V3<double>& ng, double cg) -> V3<double> {
-    const double g11 = dot(nf, nf), g12 = dot(nf, ng), g22 = dot(ng, ng);
-    const double det = g11 * g22 - g12 * g12;
-    const double al_ = (cf * g22 - cg * g12) / det, be = (cg * g11 - cf * g12) / det;
-    return {al_ * nf.x + be * ng.x, al_ * nf.y + be * ng.y, al_ * nf.z + be * ng.z};
+    const V3<double> d = cross(nf, ng);
+    const V3<double> gd = cross(ng, d), fd = cross(nf, d);
+    const double inv = 1.0 / dot(d, d);
+    return {(cf * gd.x - cg * fd.x) * inv, (cf * gd.y - cg * fd.y) * inv, (cf * gd.z - cg * fd.z) * inv};
+  };
+  // the three planes and the position of vertex slot t, in double: cached,
+  // or (exact) planes from the exact inputs, or (refined) cached or exact
+  // planes with the vertex solved and refined in double
+  auto corner_geom = [&](unsigned u, int t, bool exact, V3<double>& na, double& ca, V3<double>& nb_, double& cb,
+                         V3<double>& nc, double& cc, V3<double>& v, bool refined = false) {
+    if (exact) {
+      plane64(u & 0xFF, na, ca);
+      plane64((u >> 8) & 0xFF, nb_, cb);
+      plane64((u >> 16) & 0xFF, nc, cc);
+      v = refined ? solve3_refined(na, ca, nb_, cb, nc, cc) : solve3<double>(na, ca, nb_, cb, nc, cc);
+    } else if (refined) {
+      const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
+      na = {(double)pnx[pb + A], (double)pny[pb + A], (double)pnz[pb + A]};
+      ca = (double)pnc[pb + A];
+      nb_ = {(double)pnx[pb + B], (double)pny[pb + B], (double)pnz[pb + B]};
+      cb = (double)pnc[pb + B];
+      nc = {(double)pnx[pb + C], (double)pny[pb + C], (double)pnz[pb + C]};
+      cc = (double)pnc[pb + C];
+      v = solve3_refined(na, ca, nb_, cb, nc, cc);
+    } else {
+      const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
+      na = {(double)pnx[pb + A], (double)pny[pb + A], (double)pnz[pb + A]};
+      ca = (double)pnc[pb + A];
+      nb_ = {(double)pnx[pb + B], (double)pny[pb + B], (double)pnz[pb + B]};
+      cb = (double)pnc[pb + B];
+      nc = {(double)pnx[pb + C], (double)pny[pb + C], (double)pnz[pb + C]};
+      cc = (double)pnc[pb + C];
+      v = {(double)vx[vb + t], (double)vy[vb + t], (double)vz[vb + t]};
+    }
   };
   auto cell_volume = [&](bool on, bool exact) -> double {
     double acc = 0.0;
@@ -1001,21 +1077,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
         if (u == kEmpty) continue;
         V3<double> na, nb_, nc, v;
         double ca, cb, cc;
-        if (exact) {
-          plane64(u & 0xFF, na, ca);
-          plane64((u >> 8) & 0xFF, nb_, cb);
-          plane64((u >> 16) & 0xFF, nc, cc);
-          v = solve3<double>(na, ca, nb_, cb, nc, cc);
-        } else {
-          const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
-          na = {(double)pnx[pb + A], (double)pny[pb + A], (double)pnz[pb + A]};
-          ca = (double)pnc[pb + A];
-          nb_ = {(double)pnx[pb + B], (double)pny[pb + B], (double)pnz[pb + B]};
-          cb = (double)pnc[pb + B];
-          nc = {(double)pnx[pb + C], (double)pny[pb + C], (double)pnz[pb + C]};
-          cc = (double)pnc[pb + C];
-          v = {(double)vx[vb + t], (double)vy[vb + t], (double)vz[vb + t]};
-        }
+        corner_geom(u, t, exact, na, ca, nb_, cb, nc, cc, v);
         const V3<double> eab = anchor(na, ca, nb_, cb), ebc = anchor(nb_, cb, nc, cc), eca = anchor(nc, cc, na, ca);
         const double fa = ca / dot(na, na), fb = cb / dot(nb_, nb_), fc = cc / dot(nc, nc);
         const V3<double> Fa = {fa * na.x, fa * na.y, fa * na.z};
@@ -1040,15 +1102,103 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
       if (refine) vol = v2;
     }
   }
+  // Per-face outputs are computed in double from vertices solved in double
+  // and refined once (a vertex of nearly parallel planes is otherwise off by
+  // its conditioning times u, and so are the areas of its faces): planes
+  // cached on the FP64 path, from the exact inputs on the float path.
+  constexpr bool kExactFaces = RECHECK;
+  // Cell centroid: the corner terms of the volume split into signed
+  // tetrahedra from the seed, (0, F_f, v, e_fh) and (0, F_f, e_fg, v); the
+  // first moment of each is its volume times the mean of its corners.
+  double cmx = 0.0, cmy = 0.0, cmz = 0.0;
+  if (a.centroid) {
+    double w6 = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    auto tet = [&](const V3<double>& x, const V3<double>& y, const V3<double>& z) {
+      const double w = dot(x, cross(y, z));
+      w6 += w;
+      mx += w * (x.x + y.x + z.x);
+      my += w * (x.y + y.y + z.y);
+      mz += w * (x.z + y.z + z.z);
+    };
+    if (cert) {
+      for (int t = j; t < H; t += L) {
+        const unsigned u = tri[vb + t];
+        if (u == kEmpty) continue;
+        V3<double> na, nb_, nc, v;
+        double ca, cb, cc;
+        corner_geom(u, t, kExactFaces, na, ca, nb_, cb, nc, cc, v, true);
+        const V3<double> eab = anchor(na, ca, nb_, cb), ebc = anchor(nb_, cb, nc, cc), eca = anchor(nc, cc, na, ca);
+        const double fa = ca / dot(na, na), fb = cb / dot(nb_, nb_), fc = cc / dot(nc, nc);
+        const V3<double> Fa = {fa * na.x, fa * na.y, fa * na.z};
+        const V3<double> Fb = {fb * nb_.x, fb * nb_.y, fb * nb_.z};
+        const V3<double> Fc = {fc * nc.x, fc * nc.y, fc * nc.z};
+        tet(Fa, v, eca);
+        tet(Fa, eab, v);
+        tet(Fb, v, eab);
+        tet(Fb, ebc, v);
+        tet(Fc, v, ebc);
+        tet(Fc, eca, v);
+      }
+    }
+    const double V6 = gsumd(w6);
+    mx = gsumd(mx);
+    my = gsumd(my);
+    mz = gsumd(mz);
+    // moment / volume = (sum w m / 24) / (sum w / 6)
+    if (V6 > 0.0) {
+      cmx = p64x + mx / (4.0 * V6);
+      cmy = p64y + my / (4.0 * V6);
+      cmz = p64z + mz / (4.0 * V6);
+    }
+  }
+  // Face areas: lane j owns plane slots j, j+L, ..., the slots it writes to
+  // the neighbour list below.  A face is the fan of the volume's corner
+  // terms: the corner of vertex v on face f, between edges f^g and f^h,
+  // spans the area n_f . (v x (e_fh - e_fg)) / (2 |n_f|).  Every lane walks
+  // all vertex slots in order, so each face sums its corners in slot order.
+  constexpr int FO = PMAX / L;
+  static_assert(FO * L == PMAX, "plane slots split evenly over the lanes");
+  double farea[FO];
+#pragma unroll
+  for (int q = 0; q < FO; ++q) farea[q] = 0.0;
+  if (a.area && cert) {
+    for (int t = 0; t < H; ++t) {
+      const unsigned u = tri[vb + t];
+      if (u == kEmpty) continue;
+      const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
+      const bool oa = A % L == j, ob = B % L == j, oc = C % L == j;
+      if (!(oa || ob || oc)) continue;
+      V3<double> na, nb_, nc, v;
+      double ca, cb, cc;
+      corner_geom(u, t, kExactFaces, na, ca, nb_, cb, nc, cc, v, true);
+      const V3<double> eab = anchor(na, ca, nb_, cb), ebc = anchor(nb_, cb, nc, cc), eca = anchor(nc, cc, na, ca);
+      auto corner = [&](const V3<double>& n, const V3<double>& e1, const V3<double>& e0) -> double {
+        return dot(n, cross(v, V3<double>{e1.x - e0.x, e1.y - e0.y, e1.z - e0.z})) / (2.0 * sqrt(dot(n, n)));
+      };
+      const double xa = oa ? corner(na, eca, eab) : 0.0;
+      const double xb = ob ? corner(nb_, eab, ebc) : 0.0;
+      const double xc = oc ? corner(nc, ebc, eca) : 0.0;
+#pragma unroll
+      for (int q = 0; q < FO; ++q) {
+        const int f = j + q * L;
+        farea[q] += (A == f ? xa : 0.0) + (B == f ? xb : 0.0) + (C == f ? xc : 0.0);
+      }
+    }
+  }
   // neighbours: alive bisector planes
   int nnb = 0;
   for (int f = j; f < PMAX; f += L) nnb += cert && ((alive >> f) & 1) && pid[pb + f] >= 0;
   int ntot;
   int noff = gexcl(nnb, ntot);
   if (cert) {
-    for (int f = j; f < PMAX; f += L) {
+#pragma unroll
+    for (int q = 0; q < FO; ++q) {
+      const int f = j + q * L;
       if (((alive >> f) & 1) && pid[pb + f] >= 0) {
-        if (noff < a.max_nbr) a.nbr[(size_t)row * a.max_nbr + noff] = pid[pb + f];
+        if (noff < a.max_nbr) {
+          a.nbr[(size_t)row * a.max_nbr + noff] = pid[pb + f];
+          if (a.area) a.area[(size_t)row * a.max_nbr + noff] = farea[q];
+        }
         ++noff;
       }
     }
@@ -1091,6 +1241,12 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     a.status[row] = (uint8_t)fin;
     a.nbr_count[row] = fin == VOTESS_CELL_CERTIFIED ? ntot : 0;
     a.volume[row] = fin == VOTESS_CELL_CERTIFIED ? vol : 0.0;
+    if (a.centroid) {
+      const bool ok = fin == VOTESS_CELL_CERTIFIED;
+      a.centroid[(size_t)row * 3 + 0] = ok ? cmx : 0.0;
+      a.centroid[(size_t)row * 3 + 1] = ok ? cmy : 0.0;
+      a.centroid[(size_t)row * 3 + 2] = ok ? cmz : 0.0;
+    }
     if (a.kneeded) a.kneeded[row] = kneed;
     if (a.vcount) a.vcount[row] = fin == VOTESS_CELL_CERTIFIED ? vtot : 0;
     if (a.counters) {
@@ -1142,6 +1298,8 @@ votess_status launch_clip(const ClipLaunch& a, hipStream_t st) {
   c.vcount = a.vcount;
   c.verts = a.verts;
   c.vplanes = a.vplanes;
+  c.area = a.area;
+  c.centroid = a.centroid;
   c.counters = a.counters;
   c.stream = a.stream;
   c.cell_start = a.cell_start;

@@ -40,6 +40,31 @@ struct DualCell {
     return v;
   }
 
+  // solve() refined once against the residual c - n.v accumulated as if in
+  // twice the working precision (FMA-split products, error-free sums): a
+  // vertex of nearly parallel planes is then good to a few ulps.
+  static std::array<double, 3> solve_refined(const Pl& a, const Pl& b, const Pl& m) {
+#pragma clang fp contract(off)
+    const std::array<double, 3> v = solve(a, b, m);
+    auto resid = [&](const Pl& q) {
+      const double n[3] = {q.x, q.y, q.z};
+      double s = q.c, err = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        const double p = n[i] * v[i];
+        const double ep = std::fma(n[i], v[i], -p);
+        const double t = s - p;
+        const double z = t - s;
+        const double es = (s - (t - z)) + (-p - z);
+        s = t;
+        err += es - ep;
+      }
+      return s + err;
+    };
+    const std::array<double, 3> d = solve(Pl{a.x, a.y, a.z, resid(a), a.id}, Pl{b.x, b.y, b.z, resid(b), b.id},
+                                          Pl{m.x, m.y, m.z, resid(m), m.id});
+    return {v[0] + d[0], v[1] + d[1], v[2] + d[2]};
+  }
+
   void box(const double lo[3], const double hi[3], const double p[3]) {
     pl.clear();
     tri.clear();
@@ -118,12 +143,13 @@ struct DualCell {
       return std::array<double, 3>{a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
     };
     auto nrm = [&](int f) { return std::array<double, 3>{pl[f].x, pl[f].y, pl[f].z}; };
-    auto anchor = [&](int f, int g) {
+    auto anchor = [&](int f, int g) {  // nearest point of line f^g: see faces()
       const auto nf = nrm(f), ng = nrm(g);
-      const double g11 = dot(nf, nf), g12 = dot(nf, ng), g22 = dot(ng, ng);
-      const double det = g11 * g22 - g12 * g12;
-      const double al = (pl[f].c * g22 - pl[g].c * g12) / det, be = (pl[g].c * g11 - pl[f].c * g12) / det;
-      return std::array<double, 3>{al * nf[0] + be * ng[0], al * nf[1] + be * ng[1], al * nf[2] + be * ng[2]};
+      const auto d = crs(nf, ng), gd = crs(ng, d), fd = crs(nf, d);
+      const double inv = 1.0 / dot(d, d);
+      std::array<double, 3> e;
+      for (int k = 0; k < 3; ++k) e[k] = (pl[f].c * gd[k] - pl[g].c * fd[k]) * inv;
+      return e;
     };
     auto foot = [&](int f) {
       const auto n = nrm(f);
@@ -144,6 +170,61 @@ struct DualCell {
     }
     return vol / 6.0;
   }
+
+  // Per-plane face areas and the first moment about the seed, from the same
+  // corner terms as volume() with refined vertices: the corner of vertex v on
+  // face f between edges
+  // f^g and f^h spans n_f . (v x (e_fh - e_fg)) / (2 |n_f|), and splits into
+  // the signed tetrahedra (0, F_f, v, e_fh) and (0, F_f, e_fg, v).
+  void faces(std::vector<double>& area, double mom[3], double& vol6) const {
+    using A3 = std::array<double, 3>;
+    auto dot = [](const A3& a, const A3& b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    auto crs = [](const A3& a, const A3& b) {
+      return A3{a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    };
+    auto diff = [](const A3& x, const A3& y) { return A3{x[0] - y[0], x[1] - y[1], x[2] - y[2]}; };
+    auto nrm = [&](int f) { return A3{pl[f].x, pl[f].y, pl[f].z}; };
+    // nearest point of line f^g to the seed, (c_f (n_g x d) - c_g (n_f x d)) /
+    // |d|^2 with d = n_f x n_g: error ~ 1/sin(angle), not its square as
+    // through the 2x2 Gram system
+    auto anchor = [&](int f, int g) {
+      const A3 nf = nrm(f), ng = nrm(g);
+      const A3 d = crs(nf, ng), gd = crs(ng, d), fd = crs(nf, d);
+      const double inv = 1.0 / dot(d, d);
+      return A3{(pl[f].c * gd[0] - pl[g].c * fd[0]) * inv, (pl[f].c * gd[1] - pl[g].c * fd[1]) * inv,
+                (pl[f].c * gd[2] - pl[g].c * fd[2]) * inv};
+    };
+    auto foot = [&](int f) {
+      const A3 n = nrm(f);
+      const double s = pl[f].c / dot(n, n);
+      return A3{s * n[0], s * n[1], s * n[2]};
+    };
+    area.assign(pl.size(), 0.0);
+    mom[0] = mom[1] = mom[2] = 0.0;
+    vol6 = 0.0;
+    auto tet = [&](const A3& x, const A3& y, const A3& z) {
+      const double w = dot(x, crs(y, z));
+      vol6 += w;
+      for (int k = 0; k < 3; ++k) mom[k] += w * (x[k] + y[k] + z[k]);
+    };
+    for (size_t t = 0; t < tri.size(); ++t) {
+      const int a = tri[t][0], b = tri[t][1], c = tri[t][2];
+      const A3 v = solve_refined(pl[a], pl[b], pl[c]);
+      const A3 eab = anchor(a, b), ebc = anchor(b, c), eca = anchor(c, a);
+      const A3 na = nrm(a), nb = nrm(b), nc = nrm(c);
+      area[a] += dot(na, crs(v, diff(eca, eab))) / (2.0 * std::sqrt(dot(na, na)));
+      area[b] += dot(nb, crs(v, diff(eab, ebc))) / (2.0 * std::sqrt(dot(nb, nb)));
+      area[c] += dot(nc, crs(v, diff(ebc, eca))) / (2.0 * std::sqrt(dot(nc, nc)));
+      const A3 Fa = foot(a), Fb = foot(b), Fc = foot(c);
+      tet(Fa, v, eca);
+      tet(Fa, eab, v);
+      tet(Fb, v, eab);
+      tet(Fb, ebc, v);
+      tet(Fc, v, ebc);
+      tet(Fc, eca, v);
+    }
+    for (int k = 0; k < 3; ++k) mom[k] /= 24.0;
+  }
 };
 
 struct HostGrid {
@@ -157,7 +238,7 @@ struct HostGrid {
 };
 
 template <typename T>
-void one_cell(const T* rec, int n, const HostGrid& G, int s, bool want_vertices, HostCellOut& out) {
+void one_cell(const T* rec, int n, const HostGrid& G, int s, bool want_vertices, bool want_faces, HostCellOut& out) {
   const double p[3] = {(double)rec[4 * (size_t)s], (double)rec[4 * (size_t)s + 1], (double)rec[4 * (size_t)s + 2]};
   const votess_grid& g = G.g;
   int c[3];
@@ -220,8 +301,18 @@ void one_cell(const T* rec, int n, const HostGrid& G, int s, bool want_vertices,
   for (const auto& t : C.tri)
     for (int e = 0; e < 3; ++e) used[t[e]] = 1;
   out.nbr.clear();
+  out.area.clear();
+  std::vector<double> farea;
+  if (want_faces) {
+    double mom[3], vol6;
+    C.faces(farea, mom, vol6);
+    for (int a = 0; a < 3; ++a) out.centroid[a] = p[a] + (vol6 > 0.0 ? 6.0 * mom[a] / vol6 : 0.0);
+  }
   for (size_t f = 0; f < C.pl.size(); ++f)
-    if (used[f] && C.pl[f].id >= 0) out.nbr.push_back(C.pl[f].id);
+    if (used[f] && C.pl[f].id >= 0) {
+      out.nbr.push_back(C.pl[f].id);
+      if (want_faces) out.area.push_back(farea[f]);
+    }
   if (want_vertices) {
     for (size_t t = 0; t < C.tri.size(); ++t) {
       for (int a = 0; a < 3; ++a) out.verts.push_back(C.pos[t][a] + p[a]);
@@ -234,7 +325,7 @@ void one_cell(const T* rec, int n, const HostGrid& G, int s, bool want_vertices,
 
 void host_fallback_cells(const void* sorted_h, votess_dtype dt, int n, const votess_grid& grid,
                          const int32_t* cell_start_h, const int32_t* cells, int ncells, bool want_vertices,
-                         int threads, std::vector<HostCellOut>& out) {
+                         bool want_faces, int threads, std::vector<HostCellOut>& out) {
   out.assign(ncells, HostCellOut());
   if (ncells == 0) return;
   HostGrid G{grid, cell_start_h};
@@ -246,9 +337,9 @@ void host_fallback_cells(const void* sorted_h, votess_dtype dt, int n, const vot
       const int i = next.fetch_add(1);
       if (i >= ncells) break;
       if (dt == VOTESS_F32)
-        one_cell<float>((const float*)sorted_h, n, G, cells[i], want_vertices, out[i]);
+        one_cell<float>((const float*)sorted_h, n, G, cells[i], want_vertices, want_faces, out[i]);
       else
-        one_cell<double>((const double*)sorted_h, n, G, cells[i], want_vertices, out[i]);
+        one_cell<double>((const double*)sorted_h, n, G, cells[i], want_vertices, want_faces, out[i]);
     }
   };
   std::vector<std::thread> pool;

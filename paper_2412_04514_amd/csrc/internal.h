@@ -127,6 +127,8 @@ struct ClipLaunch {
   int32_t* vcount;
   double* verts;
   int32_t* vplanes;
+  double* area = nullptr;        // [rows, max_nbr] face areas next to nbr (nullable)
+  double* centroid = nullptr;    // [rows, 3] cell centroids (nullable)
   unsigned long long* counters;  // [8]: rechecks, unresolved, capacity, refined, streamed -- nullable
   int stream = 0;                // 1: uncertified cells continue by grid rings
   const int32_t* cell_start = nullptr;
@@ -140,9 +142,11 @@ votess_status launch_compact_failed(const uint8_t* status, const int32_t* cells,
                                     int32_t* d_count, uint8_t want_status_mask, hipStream_t st);
 
 // CSR assembly (assemble.hip)
+// area_sorted / cen_sorted (nullable) travel with their rows into area / centroid.
 votess_status launch_assemble(const int32_t* nbr_count, const int32_t* nbr, int max_nbr, const double* vol_sorted,
-                              const int32_t* perm, int n, int index_space, int64_t* row_ptr, int32_t* col,
-                              double* volume, Workspace& ws, hipStream_t st, int64_t* nnz_h);
+                              const double* area_sorted, const double* cen_sorted, const int32_t* perm, int n,
+                              int index_space, int64_t* row_ptr, int32_t* col, double* volume, double* area,
+                              double* centroid, Workspace& ws, hipStream_t st, int64_t* nnz_h);
 votess_status launch_assemble_vertices(const int32_t* vcount, const double* verts, const int32_t* vplanes,
                                        int max_vert, const int32_t* perm, int n, int index_space,
                                        int64_t* vrow_ptr, double* vxyz, int32_t* vout, Workspace& ws,
@@ -151,13 +155,15 @@ votess_status launch_assemble_vertices(const int32_t* vcount, const double* vert
 // host fallback (fallback.cpp): exact cells with unbounded k on the CPU.
 struct HostCellOut {
   std::vector<int32_t> nbr;     // sorted indices of neighbours (unordered)
+  std::vector<double> area;     // face area per entry of nbr (want_faces)
   double volume = 0.0;
+  double centroid[3] = {0.0, 0.0, 0.0};  // (want_faces)
   std::vector<double> verts;    // absolute xyz
   std::vector<int32_t> vplanes; // sorted indices or -1..-6
   bool ok = false;
 };
 void host_fallback_cells(const void* sorted_h, votess_dtype dt, int n, const votess_grid& grid,
                          const int32_t* cell_start_h, const int32_t* cells, int ncells, bool want_vertices,
-                         int threads, std::vector<HostCellOut>& out);
+                         bool want_faces, int threads, std::vector<HostCellOut>& out);
 
 }  // namespace votess

@@ -95,3 +95,56 @@ def triple_vertices(P, owner, vplanes, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
             y[:, k] = det(m) / D
         kappa = np.sqrt((n.astype(np.float64) ** 2).sum(2)).prod(1) / np.abs(D.astype(np.float64))
     return (y + pi).astype(np.float64), kappa
+
+
+# Per-face outputs.  Both precisions compute them in double from double
+# vertices.  A face area is a sum of corner terms n.(v x (e' - e)) / 2 with
+# |v|, |e|, |e'| <= R (R = the cell's farthest vertex from its generator), so
+# each term carries an absolute error of order kappa u R^2 (u = 2^-53, kappa
+# the conditioning of the vertex); the centroid is a first moment (terms of
+# order R^4) over a volume.  The oracle clips from the box, so its vertices
+# carry an absolute error of order u times the box size L, and its face areas
+# u L R (this dominates for cells far smaller than the box, as in cluster
+# cores).  Bars: area within 1e-10 relative, or 1e-12 R^2 + 2e-15 R L;
+# centroid within 1e-10 R or 1e-12 R^4 / V.
+AREA_RTOL, AREA_FLOOR, AREA_BOX = 1e-10, 1e-12, 2e-15
+CEN_RTOL, CEN_FLOOR = 1e-10, 1e-12
+
+
+def radius_of_cells(P, orc):
+    """R^2 of every cell: the largest squared distance from its generator to
+    one of its vertices, from the oracle (vertices=True)."""
+    n = len(orc["vrow_ptr"]) - 1
+    owner = np.repeat(np.arange(n), np.diff(orc["vrow_ptr"]))
+    d2 = ((orc["vxyz"] - np.asarray(P, dtype=np.float64)[owner]) ** 2).sum(1)
+    r2 = np.zeros(n)
+    np.maximum.at(r2, owner, d2)
+    return r2
+
+
+def face_errors(gpu_area, gpu_cen, orc, r2, rows=None, gpu_row_ptr=None, box_size=1.0):
+    """(area violations, centroid violations, max area ratio, max centroid
+    ratio): ratios are error / bar, for rows (default all) whose neighbour
+    lists already match the oracle's (the GPU's row_ptr is needed when the
+    oracle computed only ``rows``)."""
+    rp = orc["row_ptr"]
+    n = len(rp) - 1
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    own = np.repeat(np.arange(n), np.diff(rp))
+    sel = np.isin(own, rows)
+    a_o = orc["area"][sel]
+    if gpu_row_ptr is None:
+        a_g = np.asarray(gpu_area)[sel]
+    else:
+        grp = np.asarray(gpu_row_ptr)
+        idx = np.concatenate([np.arange(grp[i], grp[i + 1]) for i in rows]) if len(rows) else np.zeros(0, int)
+        a_g = np.asarray(gpu_area)[idx]
+    bar_a = AREA_RTOL * np.abs(a_o) + AREA_FLOOR * r2[own[sel]] + AREA_BOX * np.sqrt(r2[own[sel]]) * box_size
+    ra = np.abs(a_g - a_o) / bar_a
+    c_o = orc["centroid"][rows]
+    c_g = np.asarray(gpu_cen)[rows]
+    R = np.sqrt(r2[rows])
+    V = orc["volume"][rows]
+    bar_c = CEN_RTOL * R + CEN_FLOOR * r2[rows] ** 2 / V
+    rc = np.abs(c_g - c_o).max(axis=1) / bar_c
+    return int((ra > 1).sum()), int((rc > 1).sum()), float(ra.max(initial=0)), float(rc.max(initial=0))

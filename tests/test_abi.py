@@ -76,7 +76,7 @@ def test_host_side_validation():
     assert lib.votess_knn(None, None, 0, 10, C.byref(grid), None, None, None, None, 10, 32, 0, None, None) == 1
     opts = _lib.ClipOpts()
     assert lib.votess_clip_cells(None, None, 0, 10, C.byref(ok), None, 10, None, 32, C.byref(opts),
-                                 *([None] * 9)) == 1
+                                 *([None] * 11)) == 1
     r = _lib.Result()
     assert lib.votess_tessellate(None, None, 0, 10, C.byref(ok), None, C.byref(r), None) == 1
 
@@ -86,6 +86,7 @@ def test_params_default():
     p = _lib.Params()
     lib.votess_params_default(C.byref(p))
     assert p.k0 == 32 and p.max_gpu_retries == 1 and p.pts_per_cell == 2.0 and p.host_fallback == 1
+    assert p.want_faces == 0 and p.gpu_stream == 1
     assert abs(p.eps - 1e-6) < 1e-18
 
 

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import compare_rows, note, volume_errors
+from helpers import compare_rows, face_errors, note, radius_of_cells, volume_errors
 from oracle import features as ofeat
 from oracle import mlp
 from paper_2412_04514_amd import gen
@@ -180,6 +180,23 @@ def test_learned_gain_over_fixed_k(trained):
          f"learned knn+clip {sl['ms_knn'] + sl['ms_clip'] + sl['ms_features'] + sl['ms_mlp']:.1f} ms, "
          f"fixed {sf['ms_knn'] + sf['ms_clip']:.1f} ms")
     assert tl < tf
+
+
+def test_learned_faces(trained):
+    """Face areas and centroids through the learned first pass (FP32 clipping,
+    streaming after the buckets) against the oracle, every cell."""
+    P = gen.cluster(150_000, seed=5, dtype=np.float32)
+    pts = torch.from_numpy(P).cuda()
+    kw = dict(precision="f32", kmodel=trained, tau=0.9, max_gpu_retries=0)
+    res = vt.tessellate(pts, faces=True, **kw)
+    plain = vt.tessellate(pts, **kw)
+    assert torch.equal(res.col, plain.col) and torch.equal(res.volume, plain.volume)
+    P64 = P.astype(np.float64)
+    orc = oracle.tessellate(P64, vertices=True)
+    assert not compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
+    na, nc, ra, rc = face_errors(res.area.cpu().numpy(), res.centroid.cpu().numpy(), orc, radius_of_cells(P64, orc))
+    note(f"  learned faces: area err/bar max {ra:.3f}, centroid err/bar max {rc:.3f} stats {res.stats}")
+    assert na == 0 and nc == 0
 
 
 @pytest.mark.parametrize("cfg", ["learned-f32", "fixed-f64"])
