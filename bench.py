@@ -8,8 +8,8 @@ assembly) with the points already resident in HBM.  Prints one JSON line:
 cells/s for the headline configuration (learned-k, FP32 clipping with FP64
 rechecks, when a trained k-model is available; otherwise fixed-k FP32), the
 speedup over fixed-k FP64 on the same input, a roofline entry for the
-dominant kernel, and the CPU oracle timed on a bounded sample of the same
-workload on this machine's host cores.
+dominant kernel, the step with face areas and centroids, and the CPU oracle
+timed on a bounded sample of the same workload on this machine's host cores.
 """
 from __future__ import annotations
 
@@ -32,7 +32,7 @@ ALGO_FLOPS_PER_CELL = {"cluster-16m-f32": 32586.95}
 # HBM bytes moved by all k_clip launches of one learned-k step, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (profiles/clip_traffic_cluster16m_f32.md).
 # Valid for the clip kernel as it was measured: re-measure after changing it.
-TRAFFIC_BYTES_PER_STEP = {"cluster-16m-f32": 3.2705e10}
+TRAFFIC_BYTES_PER_STEP = {"cluster-16m-f32": 3.2615e10}
 
 PEAK = {"hbm_gbs": 8000.0, "fp32_tflops": 157.3, "fp64_tflops": 78.6}
 SORT_BYTES_PER_POINT = {np.float32: 12 + 16 + 4, np.float64: 24 + 32 + 4}  # read pts, write record + perm
@@ -59,6 +59,7 @@ def main(argv=None) -> int:
     ap.add_argument("--retries", type=int, default=0,
                     help="doublings of k after the learned pass (64 -> 128 -> 256) before the stream phase; "
                          "0: the learned pass streams its uncertified cells directly")
+    ap.add_argument("--no-faces", action="store_true", help="skip the run with face areas and centroids")
     ap.add_argument("--profile-step", action="store_true", help="one headline step only (for rocprofv3)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (calibrates rocprofv3 byte counters)")
@@ -142,6 +143,15 @@ def main(argv=None) -> int:
                               "fixed-k64 FP64")
         base["k64_ms_per_step"] = ms64b
 
+    # the headline configuration with the per-face outputs (face areas and
+    # centroids): their cost on top of the step
+    faces = None
+    if not args.no_faces:
+        msf, statsf = run(dict(headline, faces=True), 2, 1, label + " + faces")
+        faces = dict(ms_per_step=msf, cells_per_s=n / (msf / 1e3),
+                     clip_ms=float(np.mean([s["ms_clip"] for s in statsf])),
+                     assemble_ms=float(np.mean([s["ms_assemble"] for s in statsf])))
+
     # roofline of the dominant kernel (largest share of the step)
     work = {"sort": ms_sort, "knn": ms_knn + ms_feat, "clip": ms_clip}
     dom = max(work, key=work.get)
@@ -194,6 +204,7 @@ def main(argv=None) -> int:
         "fixed_k_f64": {"ms_per_step": base["ms_per_step"], "cells_per_s": base["cells_per_s"],
                         "knn_clip_ms": base["knn_clip_ms"]} if base else None,
         "speedup_vs_fixed_k64_f64": (base["k64_ms_per_step"] / ms) if base else None,
+        "with_faces": faces,
         "stage_ms": {"sort": ms_sort, "knn": ms_knn, "features": ms_feat, "mlp": ms_mlp, "clip": ms_clip,
                      "assemble": mean("ms_assemble"), "fallback": mean("ms_fallback")},
         "sort_gbs": SORT_BYTES_PER_POINT[P.dtype.type] * n / (ms_sort / 1e3) / 1e9,
