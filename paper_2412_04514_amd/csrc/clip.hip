@@ -349,7 +349,8 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
 
   // Tests plane (n, c) of candidate nb against every vertex and, if it cuts,
   // replaces the removed triangles.  Called by every lane (wave-uniform).
-  auto apply_plane = [&](bool run, R nx, R ny, R nz, R c, R d2, int nb) {
+  // Always inlined: as a call, its captures live in scratch memory.
+  auto apply_plane = [&](bool run, R nx, R ny, R nz, R c, R d2, int nb) __attribute__((always_inline)) {
     // ---- test the plane against every vertex
     unsigned out = 0;
     bool unresolved = false;
