@@ -142,6 +142,13 @@ def main(argv=None) -> int:
         ms64b, stats64b = run(dict(precision="f64", k0=64, max_gpu_retries=0), max(1, args.steps // 2), 1,
                               "fixed-k64 FP64")
         base["k64_ms_per_step"] = ms64b
+    # ablation of the network: the FP32 form at fixed k = 64, streaming after the list
+    abl = None
+    if kmodel is not None and not args.no_baseline_f64:
+        msa, statsa = run(dict(precision="f32", k0=64, max_gpu_retries=0), 2, 1, "fixed-k64 FP32")
+        abl = dict(ms_per_step=msa, cells_per_s=n / (msa / 1e3),
+                   knn_ms=float(np.mean([s["ms_knn"] for s in statsa])),
+                   clip_ms=float(np.mean([s["ms_clip"] for s in statsa])))
 
     # the headline configuration with the per-face outputs (face areas and
     # centroids): their cost on top of the step
@@ -204,6 +211,7 @@ def main(argv=None) -> int:
         "fixed_k_f64": {"ms_per_step": base["ms_per_step"], "cells_per_s": base["cells_per_s"],
                         "knn_clip_ms": base["knn_clip_ms"]} if base else None,
         "speedup_vs_fixed_k64_f64": (base["k64_ms_per_step"] / ms) if base else None,
+        "fixed_k64_f32": abl,
         "with_faces": faces,
         "stage_ms": {"sort": ms_sort, "knn": ms_knn, "features": ms_feat, "mlp": ms_mlp, "clip": ms_clip,
                      "assemble": mean("ms_assemble"), "fallback": mean("ms_fallback")},

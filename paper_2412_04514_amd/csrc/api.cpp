@@ -533,7 +533,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     }
     // radius failures retry at 2k; capacity overflows go to the large kernel
     VT_TRY(launch_compact_failed(status.get<uint8_t>(), nullptr, n, cur, ctx->d_counter,
-                                 (1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY), st));
+                                 (1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY), ctx->ws, st));
     VT_HIP(hipMemcpyAsync(&nfail, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
     VT_HIP(hipStreamSynchronize(st));
     if (!P.kmodel && S.npasses < VOTESS_MAX_PASSES) S.pass_failed[S.npasses++] = nfail;
@@ -543,7 +543,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   auto capacity_pass = [&](const int32_t* ids, int cnt, int kk, bool strm) -> votess_status {
     int ncap = 0;
     VT_TRY(launch_compact_failed(status.get<uint8_t>(), ids, cnt, nxt, ctx->d_counter, 1u << VOTESS_CELL_CAPACITY,
-                                 st));
+                                 ctx->ws, st));
     VT_HIP(hipMemcpyAsync(&ncap, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
     VT_HIP(hipStreamSynchronize(st));
     if (ncap == 0) return VOTESS_OK;
@@ -586,7 +586,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     VT_TRY(capacity_pass(cur, nfail, k, stream_last && r == nretry - 1));
     const int cells_in = nfail;
     VT_TRY(launch_compact_failed(status.get<uint8_t>(), cur, nfail, nxt, ctx->d_counter,
-                                 (1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY), st));
+                                 (1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY), ctx->ws, st));
     VT_HIP(hipMemcpyAsync(&nfail, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
     VT_HIP(hipStreamSynchronize(st));
     if (S.npasses < VOTESS_MAX_PASSES) {
@@ -603,7 +603,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   if (n > 0) {
     VT_TRY(launch_compact_failed(status.get<uint8_t>(), nullptr, n, nxt, ctx->d_counter,
                                  (1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY) |
-                                     (1u << VOTESS_CELL_UNRESOLVED),
+                                     (1u << VOTESS_CELL_UNRESOLVED), ctx->ws,
                                  st));
     VT_HIP(hipMemcpyAsync(&nhost, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
     unsigned long long cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};

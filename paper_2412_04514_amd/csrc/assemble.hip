@@ -1,4 +1,4 @@
-// Retry compaction (cells whose certificate failed) and output assembly: the
+// Retry compaction (cells whose certificate failed, in order) and output assembly: the
 // per-cell neighbour lists become one CSR "jagged array" of neighbour indices
 // (paper, Features section), rows in original input order by default or in
 // grid-sorted order, each row ascending; volumes, face areas, centroids and
@@ -8,24 +8,73 @@
 namespace votess {
 namespace {
 
-// Cells of `cells` (or 0..nc-1) whose status bit is in `mask`, appended to out
-// with one atomic per wave (order across waves is not fixed; every consumer
-// writes per-cell results by cell id).
-__global__ __launch_bounds__(256) void k_compact(const uint8_t* __restrict__ status, const int* __restrict__ cells,
-                                                 int nc, unsigned mask, int* __restrict__ out,
-                                                 int* __restrict__ count) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int id = 0;
-  bool take = false;
-  if (t < nc) {
-    id = cells ? cells[t] : t;
-    take = (mask >> status[id]) & 1u;
-  }
+// Cells of `cells` (or 0..nc-1) whose status bit is in `mask`, written to out
+// in their input order, so that a compacted list of grid-sorted cells stays
+// grid-sorted (neighbouring queries share cache lines in the k-NN and clip).
+// Three steps: per-block counts, one scan of the counts, per-block writes.
+constexpr int kCompactBlock = 256;
+
+__device__ __forceinline__ bool compact_take(const uint8_t* __restrict__ status, const int* __restrict__ cells,
+                                             int nc, unsigned mask, int t, int& id) {
+  id = 0;
+  if (t >= nc) return false;
+  id = cells ? cells[t] : t;
+  return (mask >> status[id]) & 1u;
+}
+
+__global__ __launch_bounds__(kCompactBlock) void k_compact_count(const uint8_t* __restrict__ status,
+                                                                 const int* __restrict__ cells, int nc,
+                                                                 unsigned mask, int* __restrict__ bcount) {
+  __shared__ int wsum[kCompactBlock / 64];
+  int id;
+  const bool take = compact_take(status, cells, nc, mask, blockIdx.x * kCompactBlock + threadIdx.x, id);
   const unsigned long long b = __ballot(take);
-  const int lane = threadIdx.x & 63;
-  int base = 0;
-  if (lane == 0 && b) base = atomicAdd(count, __popcll(b));
-  base = __shfl(base, 0, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < kCompactBlock / 64; ++w) s += wsum[w];
+    bcount[blockIdx.x] = s;
+  }
+}
+
+// Exclusive scan of nb block counts in place (one block), total to *count.
+__global__ __launch_bounds__(1024) void k_compact_scan(int* __restrict__ bcount, int nb, int* __restrict__ count) {
+  __shared__ int part[1024];
+  const int per = (nb + 1023) / 1024;
+  const int b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+  int s = 0;
+  for (int i = b0; i < b1; ++i) s += bcount[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {  // Hillis-Steele inclusive scan of the per-thread sums
+    const int v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - s;
+  for (int i = b0; i < b1; ++i) {
+    const int c = bcount[i];
+    bcount[i] = run;
+    run += c;
+  }
+  if (threadIdx.x == 1023) *count = part[1023];
+}
+
+__global__ __launch_bounds__(kCompactBlock) void k_compact_write(const uint8_t* __restrict__ status,
+                                                                 const int* __restrict__ cells, int nc,
+                                                                 unsigned mask, const int* __restrict__ boff,
+                                                                 int* __restrict__ out) {
+  __shared__ int wsum[kCompactBlock / 64];
+  int id;
+  const bool take = compact_take(status, cells, nc, mask, blockIdx.x * kCompactBlock + threadIdx.x, id);
+  const unsigned long long b = __ballot(take);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wsum[w] = __popcll(b);
+  __syncthreads();
+  int base = boff[blockIdx.x];
+  for (int v = 0; v < w; ++v) base += wsum[v];
   if (take) out[base + __popcll(b & ((1ull << lane) - 1ull))] = id;
 }
 
@@ -98,11 +147,23 @@ __global__ void k_vrows_fill(const int* __restrict__ vcount, const double* __res
 }  // namespace
 
 votess_status launch_compact_failed(const uint8_t* status, const int32_t* cells, int nc, int32_t* out_cells,
-                                    int32_t* d_count, uint8_t want_status_mask, hipStream_t st) {
-  VT_HIP(hipMemsetAsync(d_count, 0, sizeof(int), st));
-  if (nc == 0) return VOTESS_OK;
-  k_compact<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(status, cells, nc, want_status_mask, out_cells, d_count);
+                                    int32_t* d_count, uint8_t want_status_mask, Workspace& ws, hipStream_t st) {
+  if (nc <= 0) {
+    VT_HIP(hipMemsetAsync(d_count, 0, sizeof(int), st));
+    return VOTESS_OK;
+  }
+  const int nb = (nc + kCompactBlock - 1) / kCompactBlock;
+  const size_t mark = ws.used;
+  const size_t need = Workspace::align(ws.used) + (size_t)nb * sizeof(int);
+  if (need > ws.cap) return fail(VOTESS_ENOMEM, "compaction: workspace of %zu bytes < %zu", ws.cap, need);
+  int* bcount = ws.take<int>(nb);
+  k_compact_count<<<(unsigned)nb, kCompactBlock, 0, st>>>(status, cells, nc, want_status_mask, bcount);
   VT_HIP(hipGetLastError());
+  k_compact_scan<<<1, 1024, 0, st>>>(bcount, nb, d_count);
+  VT_HIP(hipGetLastError());
+  k_compact_write<<<(unsigned)nb, kCompactBlock, 0, st>>>(status, cells, nc, want_status_mask, bcount, out_cells);
+  VT_HIP(hipGetLastError());
+  ws.used = mark;  // the stream orders the kernels before any later use of the space
   return VOTESS_OK;
 }
 

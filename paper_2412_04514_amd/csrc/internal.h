@@ -138,8 +138,9 @@ struct ClipLaunch {
 votess_status launch_clip(const ClipLaunch& a, hipStream_t st);
 
 // compaction of cells by status (assemble.hip)
+// order-preserving; takes nc/256 ints of `ws` for the duration of its kernels
 votess_status launch_compact_failed(const uint8_t* status, const int32_t* cells, int nc, int32_t* out_cells,
-                                    int32_t* d_count, uint8_t want_status_mask, hipStream_t st);
+                                    int32_t* d_count, uint8_t want_status_mask, Workspace& ws, hipStream_t st);
 
 // CSR assembly (assemble.hip)
 // area_sorted / cen_sorted (nullable) travel with their rows into area / centroid.

@@ -565,7 +565,7 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
     int cnt = 0;
     // the compaction takes a status mask; bucket values are 0..6, so bit b selects bucket b
     rc = launch_compact_failed((const uint8_t*)bucket, nullptr, n, cells_buf, ctx->d_counter,
-                               (uint8_t)(1u << b), st);
+                               (uint8_t)(1u << b), ctx->ws, st);
     if (rc != VOTESS_OK) break;
     if (hipMemcpyAsync(&cnt, ctx->d_counter, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
