@@ -566,14 +566,28 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     }
   };
 
+  // The list is read two planes ahead (the index of plane m+2, the record of
+  // plane m+1), so that the two dependent loads of a plane overlap the work
+  // of the one before it.
+  const int* klist = a.knn + (size_t)(have ? t_idx : 0) * a.k;
+  int nb_next = have && a.k > 0 ? klist[0] : -1;
+  Rec4 q_next = rec[nb_next >= 0 ? nb_next : sid];
+  int nb_next2 = have && a.k > 1 ? klist[1] : -1;
   int m = 0;
   for (; m < a.k; ++m) {
     bool run = st == ST_RUN;
     if (!__any(run)) break;
     int nb = -1;
     R nx = 0, ny = 0, nz = 0, d2 = 0, c = 0;
+    const int nb_cur = nb_next;
+    const Rec4 q_cur = q_next;
     if (run) {
-      nb = a.knn[(size_t)t_idx * a.k + m];
+      nb_next = nb_next2;
+      q_next = rec[nb_next >= 0 ? nb_next : sid];
+      nb_next2 = m + 2 < a.k ? klist[m + 2] : -1;
+    }
+    if (run) {
+      nb = nb_cur;
       if (nb < 0) {  // padded list: it holds every other point
         st = VOTESS_CELL_CERTIFIED;
         kneed = m;
@@ -582,7 +596,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs a) {
     }
     bool cert_check = false, cert_recheck = false;
     if (run) {
-      const Rec4 q = rec[nb];
+      const Rec4 q = q_cur;
       nx = (R)q.x - px;
       ny = (R)q.y - py;
       nz = (R)q.z - pz;
