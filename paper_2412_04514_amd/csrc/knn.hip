@@ -37,6 +37,7 @@ struct KeyOps<float> {
   __device__ static double d2(Key a) { return (double)__uint_as_float((unsigned)(a >> 32)); }
   __device__ static int idx(Key a) { return a == ~0ull ? -1 : (int)(unsigned)(a & 0xffffffffu); }
   __device__ static Key shfl(Key a, int src) { return __shfl(a, src, 64); }
+  __device__ static Key shfl_xor(Key a, int m) { return __shfl_xor(a, m, 64); }
 };
 template <>
 struct KeyOps<double> {
@@ -51,6 +52,7 @@ struct KeyOps<double> {
   __device__ static double d2(const Key& a) { return a.d; }
   __device__ static int idx(const Key& a) { return a.i == INT_MAX ? -1 : a.i; }
   __device__ static Key shfl(const Key& a, int src) { return {__shfl(a.d, src, 64), __shfl(a.i, src, 64)}; }
+  __device__ static Key shfl_xor(const Key& a, int m) { return {__shfl_xor(a.d, m, 64), __shfl_xor(a.i, m, 64)}; }
 };
 
 // Ascending list of K keys over a group of G lanes: lane l holds ranks
@@ -81,6 +83,40 @@ struct GroupList {
       key[e] = p < c ? key[e] : (p == c ? x : below);
     }
   }
+  // Sorts the K keys ascending in place (K and E powers of two): a bitonic
+  // network over positions i = l E + e, exchanges inside a lane in
+  // registers, across lanes by shuffles.  Keys are distinct (the index is
+  // part of the key), so the result is the same as inserting them one by one.
+  __device__ void sort(int l) {
+#pragma unroll
+    for (int ks = 2; ks <= G * E; ks <<= 1) {
+#pragma unroll
+      for (int js = ks >> 1; js > 0; js >>= 1) {
+        if (js < E) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int pe = e ^ js;
+            if (pe > e) {
+              const bool up = ((l * E + e) & ks) == 0;
+              const Key a = key[e], b = key[pe];
+              const bool sw = up ? O::less(b, a) : O::less(a, b);
+              key[e] = sw ? b : a;
+              key[pe] = sw ? a : b;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int i = l * E + e;
+            const Key o = O::shfl_xor(key[e], js / E);
+            const bool keep_min = (((i & ks) == 0) == ((i & js) == 0));
+            const bool o_less = O::less(o, key[e]);
+            key[e] = (keep_min == o_less) ? o : key[e];
+          }
+        }
+      }
+    }
+  }
 };
 
 template <typename T, typename D, int K, int GS>
@@ -108,6 +144,15 @@ __global__ __launch_bounds__(256) void k_knn(const typename Rec<T>::type* __rest
   GroupList<D, GS, E> L;
   L.init();
   Key wk = O::inf();  // the list's k-th key (group-uniform)
+  // The first K candidates are not inserted one by one: they are gathered in
+  // LDS (per group, in scan order) and sorted once: float keys, K <= 64 and
+  // K, E powers of two (larger networks no longer stay in registers).
+  constexpr bool kSortFill = sizeof(Key) == 8 && K <= 64 && ((K & (K - 1)) == 0) && ((E & (E - 1)) == 0);
+  constexpr int FB = kSortFill ? (256 / GS) * K : 1;
+  __shared__ Key sfill[FB];
+  Key* gfill = sfill + (kSortFill ? ((threadIdx.x & 255) / GS) * K : 0);
+  bool filling = kSortFill;
+  int nfill = 0;
   const double p0 = (double)pr.x, p1 = (double)pr.y, p2 = (double)pr.z;
   const unsigned long long gmask = (GS == 64) ? ~0ull : ((1ull << GS) - 1ull);
 
@@ -116,11 +161,28 @@ __global__ __launch_bounds__(256) void k_knn(const typename Rec<T>::type* __rest
     for (int base = jb; base < je; base += GS) {
       const int j = base + l;
       Key ck = O::inf();
-      if (j < je && j != s) {
+      const bool valid = j < je && j != s;
+      if (valid) {
         const auto qr = rec[j];
         ck = O::make(dist2_nc((D)qr.x - px, (D)qr.y - py, (D)qr.z - pz), j);
       }
-      bool pass = O::less(ck, wk);
+      bool pass;
+      if (kSortFill && filling) {
+        const unsigned long long vm = (__ballot(valid) >> gb) & gmask;
+        const int pos = nfill + __popcll(vm & ((1ull << l) - 1ull));
+        if (valid && pos < K) gfill[pos] = ck;
+        nfill += __popcll(vm);
+        if (nfill < K) continue;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int e = 0; e < E; ++e) L.key[e] = gfill[l * E + e];
+        L.sort(l);
+        wk = L.worst(gb);
+        filling = false;
+        pass = valid && pos >= K && O::less(ck, wk);  // the batch's candidates past the first K
+      } else {
+        pass = O::less(ck, wk);
+      }
       unsigned long long m = (__ballot(pass) >> gb) & gmask;
       while (m) {
         const int b = __ffsll((long long)m) - 1;
@@ -190,6 +252,15 @@ __global__ __launch_bounds__(256) void k_knn(const typename Rec<T>::type* __rest
         const int row = G.g0 * (y + G.g1 * z);
         scan(cell_start[row + bx0], cell_start[row + bx1 + 1]);
       }
+  }
+
+  if (kSortFill && filling) {  // fewer than K other points: sort what there is
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+    for (int e = 0; e < E; ++e) L.key[e] = l * E + e < nfill ? gfill[l * E + e] : O::inf();
+    L.sort(l);
+    wk = L.worst(gb);
+    filling = false;
   }
 
   // ---- phase B: every other grid cell / sub-cell row that meets the ball of
