@@ -364,10 +364,10 @@ votess_status dispatch_k(int k, const void* sorted, int n, const GridDev& G, con
     VT_KNN_CASE(16, 4)
     VT_KNN_CASE(24, 8)
     VT_KNN_CASE(32, 8)
-    VT_KNN_CASE(48, 8)
-    VT_KNN_CASE(64, 8)
+    VT_KNN_CASE(48, 16)
+    VT_KNN_CASE(64, 16)
     VT_KNN_CASE(128, 16)
-    VT_KNN_CASE(256, 16)
+    VT_KNN_CASE(256, 32)
     default:
       return fail(VOTESS_EINVAL, "knn: k=%d has no kernel (k must be one of 8,12,16,24,32,48,64,128,256)", k);
   }
