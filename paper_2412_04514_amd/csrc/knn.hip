@@ -38,6 +38,7 @@ struct KeyOps<float> {
   __device__ static int idx(Key a) { return a == ~0ull ? -1 : (int)(unsigned)(a & 0xffffffffu); }
   __device__ static Key shfl(Key a, int src) { return __shfl(a, src, 64); }
   __device__ static Key shfl_xor(Key a, int m) { return __shfl_xor(a, m, 64); }
+  __device__ static Key pick(bool c, Key a, Key b) { return c ? a : b; }
 };
 template <>
 struct KeyOps<double> {
@@ -53,6 +54,9 @@ struct KeyOps<double> {
   __device__ static int idx(const Key& a) { return a.i == INT_MAX ? -1 : a.i; }
   __device__ static Key shfl(const Key& a, int src) { return {__shfl(a.d, src, 64), __shfl(a.i, src, 64)}; }
   __device__ static Key shfl_xor(const Key& a, int m) { return {__shfl_xor(a.d, m, 64), __shfl_xor(a.i, m, 64)}; }
+  // field by field: a choice between two structs as lvalues would select
+  // their addresses and keep the list in scratch memory
+  __device__ static Key pick(bool c, const Key& a, const Key& b) { return {c ? a.d : b.d, c ? a.i : b.i}; }
 };
 
 // Ascending list of K keys over a group of G lanes: lane l holds ranks
@@ -79,8 +83,8 @@ struct GroupList {
 #pragma unroll
     for (int e = E - 1; e >= 0; --e) {
       const int p = l * E + e;
-      const Key below = e > 0 ? key[e > 0 ? e - 1 : 0] : prev;
-      key[e] = p < c ? key[e] : (p == c ? x : below);
+      const Key below = O::pick(e > 0, key[e > 0 ? e - 1 : 0], prev);
+      key[e] = O::pick(p < c, key[e], O::pick(p == c, x, below));
     }
   }
   // Sorts the K keys ascending in place (K and E powers of two): a bitonic
@@ -100,8 +104,8 @@ struct GroupList {
               const bool up = ((l * E + e) & ks) == 0;
               const Key a = key[e], b = key[pe];
               const bool sw = up ? O::less(b, a) : O::less(a, b);
-              key[e] = sw ? b : a;
-              key[pe] = sw ? a : b;
+              key[e] = O::pick(sw, b, a);
+              key[pe] = O::pick(sw, a, b);
             }
           }
         } else {
@@ -111,7 +115,7 @@ struct GroupList {
             const Key o = O::shfl_xor(key[e], js / E);
             const bool keep_min = (((i & ks) == 0) == ((i & js) == 0));
             const bool o_less = O::less(o, key[e]);
-            key[e] = (keep_min == o_less) ? o : key[e];
+            key[e] = O::pick(keep_min == o_less, o, key[e]);
           }
         }
       }
@@ -145,9 +149,10 @@ __global__ __launch_bounds__(256) void k_knn(const typename Rec<T>::type* __rest
   L.init();
   Key wk = O::inf();  // the list's k-th key (group-uniform)
   // The first K candidates are not inserted one by one: they are gathered in
-  // LDS (per group, in scan order) and sorted once: float keys, K <= 64 and
-  // K, E powers of two (larger networks no longer stay in registers).
-  constexpr bool kSortFill = sizeof(Key) == 8 && K <= 64 && ((K & (K - 1)) == 0) && ((E & (E - 1)) == 0);
+  // LDS (per group, in scan order) and sorted once: K and E powers of two,
+  // K <= 64 for float keys and <= 32 for (double, index) keys (larger
+  // networks no longer stay in registers).
+  constexpr bool kSortFill = K <= (sizeof(Key) == 8 ? 64 : 32) && ((K & (K - 1)) == 0) && ((E & (E - 1)) == 0);
   constexpr int FB = kSortFill ? (256 / GS) * K : 1;
   __shared__ Key sfill[FB];
   Key* gfill = sfill + (kSortFill ? ((threadIdx.x & 255) / GS) * K : 0);
@@ -257,7 +262,7 @@ __global__ __launch_bounds__(256) void k_knn(const typename Rec<T>::type* __rest
   if (kSortFill && filling) {  // fewer than K other points: sort what there is
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-    for (int e = 0; e < E; ++e) L.key[e] = l * E + e < nfill ? gfill[l * E + e] : O::inf();
+    for (int e = 0; e < E; ++e) L.key[e] = O::pick(l * E + e < nfill, gfill[l * E + e], O::inf());
     L.sort(l);
     wk = L.worst(gb);
     filling = false;
