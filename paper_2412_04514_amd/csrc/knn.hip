@@ -123,8 +123,10 @@ struct GroupList {
   }
 };
 
+// Held to 5 waves per SIMD (96 VGPRs, ~100 bytes per lane of spills): the
+// search is latency-bound, and the fifth wave measured ~8% faster than four.
 template <typename T, typename D, int K, int GS>
-__global__ __launch_bounds__(256) void k_knn(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_knn(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
                                              const int* __restrict__ cell_start, SubGrid sub,
                                              const int* __restrict__ queries, int nq, int* __restrict__ knn,
                                              unsigned* __restrict__ err) {
