@@ -273,7 +273,10 @@ VOTESS_API void votess_params_default(votess_params* p_h);
  * then the host fallback (exact CPU cell, unbounded k) for cells still
  * uncertified, then CSR assembly.  `pts` [n,3] dtype device, input order.
  * Rows of the result are in original order (or sorted order with
- * index_space = 1), neighbours ascending. */
+ * index_space = 1), neighbours ascending; with want_faces, area[e] is the
+ * area of the face the row's cell shares with col[e], and centroid the
+ * cells' centres of mass, both computed in double.  The result's device
+ * buffers belong to the caller: free them with votess_result_free. */
 VOTESS_API votess_status votess_tessellate(votess_ctx* ctx, const void* pts, votess_dtype dtype, int64_t n,
                                 const votess_box* box, const votess_params* params, votess_result* out_h,
                                 void* stream);
