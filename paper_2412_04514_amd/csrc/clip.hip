@@ -1329,16 +1329,18 @@ votess_status launch_clip(const ClipLaunch& a, hipStream_t st) {
   if (a.stream && (a.knn_dist == VOTESS_F32) != f32)
     return fail(VOTESS_EINVAL, "clip: the stream phase needs k-lists built in the clip precision");
   if (a.stream && !a.cell_start) return fail(VOTESS_EINVAL, "clip: the stream phase needs cell_start");
-  // 16 lanes per cell in both kernels: measured faster than 8 (fewer cells
+  // the fast kernel: 16 lanes per cell, measured faster than 8 (fewer cells
   // per wave diverge in the stream phase) and than 4 or 32
   if (a.capacity == 0) {
     if (f32) return run<float, float, 16, 64, 32, true>(c, st);
     if (a.dtype == VOTESS_F32) return run<float, double, 16, 64, 32, false>(c, st);
     return run<double, double, 16, 64, 32, false>(c, st);
   }
-  if (f32) return run<float, float, 16, 256, 64, true>(c, st);
-  if (a.dtype == VOTESS_F32) return run<float, double, 16, 256, 64, false>(c, st);
-  return run<double, double, 16, 256, 64, false>(c, st);
+  // the large-capacity kernel: 32 lanes per cell (two cells per wave keep its
+  // LDS per workgroup low enough for more than one wave per SIMD)
+  if (f32) return run<float, float, 32, 256, 64, true>(c, st);
+  if (a.dtype == VOTESS_F32) return run<float, double, 32, 256, 64, false>(c, st);
+  return run<double, double, 32, 256, 64, false>(c, st);
 }
 
 }  // namespace votess

@@ -372,7 +372,7 @@ votess_status dispatch_k(int k, const void* sorted, int n, const GridDev& G, con
     VT_KNN_CASE(24, 8)
     VT_KNN_CASE(32, 8)
     VT_KNN_CASE(48, 16)
-    VT_KNN_CASE(64, 16)
+    VT_KNN_CASE(64, 8)
     VT_KNN_CASE(128, 16)
     VT_KNN_CASE(256, 32)
     default:
