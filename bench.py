@@ -32,7 +32,7 @@ ALGO_FLOPS_PER_CELL = {"cluster-16m-f32": 32586.95}
 # HBM bytes moved by all k_clip launches of one learned-k step, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (profiles/clip_traffic_cluster16m_f32.md).
 # Valid for the clip kernel as it was measured: re-measure after changing it.
-TRAFFIC_BYTES_PER_STEP = {"cluster-16m-f32": 7.4799e10}
+TRAFFIC_BYTES_PER_STEP = {"cluster-16m-f32": 4.9143e10}
 
 PEAK = {"hbm_gbs": 8000.0, "fp32_tflops": 157.3, "fp64_tflops": 78.6}
 SORT_BYTES_PER_POINT = {np.float32: 12 + 16 + 4, np.float64: 24 + 32 + 4}  # read pts, write record + perm

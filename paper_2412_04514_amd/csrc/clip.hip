@@ -193,7 +193,7 @@ __device__ __forceinline__ void plane64_of(int id, const Rec4* rec, double px, d
 
 // The fast kernels (TMAX = 64) are held to 3 waves per SIMD: the compiler
 // would otherwise give the stream variants ~225 VGPRs (2 waves), and with
-// the third wave hiding load latency they run ~20% faster despite ~140 bytes
+// the third wave hiding load latency they run ~20% faster despite ~90 bytes
 // per lane of spills.
 template <typename P, typename R, int L, int TMAX, int PMAX, bool RECHECK, bool STREAM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ? 3 : 1))) void k_clip(ClipArgs a) {
@@ -222,6 +222,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   // sub-grid origin and sub-cell widths), per group
   constexpr int DG = STREAM ? G * 9 : 1;
   __shared__ double dgeo[DG];
+  // stream phase: the flower box in coordinates, per group (read only when a
+  // dense cell is entered, so it need not occupy registers)
+  constexpr int FWG = STREAM ? G * 6 : 1;
+  __shared__ double fwbox[FWG];
 
   const Rec4* rec = (const Rec4*)a.rec;
   const int lane = threadIdx.x;
@@ -686,7 +690,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     }
     // flower box in grid cells, from the current vertices (group reduction)
     int fb0 = 0, fb1 = -1, fb2 = 0, fb3 = -1, fb4 = 0, fb5 = -1;
-    double fw0 = 0, fw1 = 0, fw2 = 0, fw3 = 0, fw4 = 0, fw5 = 0;  // the same box in coordinates
+    double* fwb = fwbox + (STREAM ? g * 6 : 0);  // the same box in coordinates
     auto flower_box = [&]() {
       double mn0 = 1e300, mn1 = 1e300, mn2 = 1e300, mx0 = -1e300, mx1 = -1e300, mx2 = -1e300;
       for (int t = j; t < H; t += L) {
@@ -703,9 +707,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
         mn1 = fmin(mn1, shfl_xor_w(mn1, o, L)); mx1 = fmax(mx1, shfl_xor_w(mx1, o, L));
         mn2 = fmin(mn2, shfl_xor_w(mn2, o, L)); mx2 = fmax(mx2, shfl_xor_w(mx2, o, L));
       }
-      fw0 = p64x + mn0 - gmarg; fw1 = p64x + mx0 + gmarg;
-      fw2 = p64y + mn1 - gmarg; fw3 = p64y + mx1 + gmarg;
-      fw4 = p64z + mn2 - gmarg; fw5 = p64z + mx2 + gmarg;
+      const double fw0 = p64x + mn0 - gmarg, fw1 = p64x + mx0 + gmarg;
+      const double fw2 = p64y + mn1 - gmarg, fw3 = p64y + mx1 + gmarg;
+      const double fw4 = p64z + mn2 - gmarg, fw5 = p64z + mx2 + gmarg;
+      if (j == 0) {
+        fwb[0] = fw0; fwb[1] = fw1; fwb[2] = fw2; fwb[3] = fw3; fwb[4] = fw4; fwb[5] = fw5;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       fb0 = axis_cell(fw0, Gd.lo0, Gd.ih0, Gd.g0);
       fb1 = axis_cell(fw1, Gd.lo0, Gd.ih0, Gd.g0);
       fb2 = axis_cell(fw2, Gd.lo1, Gd.ih1, Gd.g1);
@@ -868,12 +876,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
                 // dense cell rx: its sub-cells inside the flower box
                 const int2 info = a.sub.info[rrow + rx];
                 const SubCell sc = sub_cell(a.sub.start + info.x);
-                dsx0 = sub_axis(fw0, sc.lo0, sc.ih0, sc.m0);
-                dsx1 = sub_axis(fw1, sc.lo0, sc.ih0, sc.m0);
-                dsy0 = sub_axis(fw2, sc.lo1, sc.ih1, sc.m1);
-                dsy1 = sub_axis(fw3, sc.lo1, sc.ih1, sc.m1);
-                dsz0 = sub_axis(fw4, sc.lo2, sc.ih2, sc.m2);
-                dsz1 = sub_axis(fw5, sc.lo2, sc.ih2, sc.m2);
+                dsx0 = sub_axis(fwb[0], sc.lo0, sc.ih0, sc.m0);
+                dsx1 = sub_axis(fwb[1], sc.lo0, sc.ih0, sc.m0);
+                dsy0 = sub_axis(fwb[2], sc.lo1, sc.ih1, sc.m1);
+                dsy1 = sub_axis(fwb[3], sc.lo1, sc.ih1, sc.m1);
+                dsz0 = sub_axis(fwb[4], sc.lo2, sc.ih2, sc.m2);
+                dsz1 = sub_axis(fwb[5], sc.lo2, sc.ih2, sc.m2);
                 {
                   // the sub-block's box (edge sub-cells reach the cell's faces)
                   const double cxl = Gd.lo0 + rx * Gd.h0, cyl = Gd.lo1 + yy * Gd.h1, czl = Gd.lo2 + zz * Gd.h2;
