@@ -282,7 +282,7 @@ VOTESS_API votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
                                 void* stream);
 VOTESS_API void votess_result_free(votess_ctx* ctx, votess_result* res_h);
 
-/* ---------------------------------------------- learned k (BASELINE forms) */
+/* -------------------------------------------- learned list size (k-model) */
 
 #define VOTESS_NFEAT 12
 #define VOTESS_NHID 64
