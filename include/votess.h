@@ -115,8 +115,8 @@ VOTESS_API votess_status votess_ctx_errors(votess_ctx* ctx, void* stream, uint32
 
 /* ---------------------------------------------------------- grid sort (a1-a3) */
 
-/* Grid with about `pts_per_cell` points per grid cell (paper, Summary: "the
- * input set of points is sorted into a grid"): per axis
+/* Grid with about `pts_per_cell` points per grid cell (paper, Summary section:
+ * the points are first binned into a uniform grid): per axis
  * g_a = max(1, round(ext_a * (n / (pts_per_cell * vol))^(1/3))).  Host only. */
 VOTESS_API votess_status votess_grid_plan(int64_t n, const votess_box* box, double pts_per_cell, votess_grid* out_h);
 
@@ -152,8 +152,9 @@ VOTESS_API int64_t votess_sub_capacity(int64_t n);
 
 /* ------------------------------------------------------------- k-NN (a4) */
 
-/* The k nearest other points of each query (paper, Summary: "a k-nearest
- * neighbors search is performed"), by a shell-expanding search over the grid.
+/* The k nearest other points of each query (paper, Summary section: the
+ * neighbour search after the grid sort), by a shell-expanding search over the
+ * grid.
  *   sorted, cell_start, subinfo, sub_start  from votess_grid_sort (the last
  *              two nullable: dense cells are then scanned whole)
  *   queries    [nq] sorted indices, or NULL for all n points (nq = n)
@@ -251,6 +252,9 @@ typedef struct {
   int64_t streamed_cells;   /* cells certified by the GPU stream phase */
   int64_t bucket_cells[8];  /* learned-k: cells per bucket */
   double ms_sort, ms_knn, ms_clip, ms_features, ms_mlp, ms_assemble, ms_fallback, ms_total;
+  /* per pass: cells its list left uncertified that went on into the stream
+   * phase (pass_failed counts the cells still uncertified after it) */
+  int64_t pass_streamed[VOTESS_MAX_PASSES];
 } votess_stats;
 
 typedef struct {
@@ -323,6 +327,33 @@ VOTESS_API votess_status votess_kmodel_train_step(votess_kmodel* m, const float*
 /* Bucket per query: least b with P(label <= b) >= tau; bucket [nq] u8 out. */
 VOTESS_API votess_status votess_kmodel_choose(votess_kmodel* m, const float* feats, int64_t nq, float tau, uint8_t* bucket,
                                    void* stream);
+
+/* Training labels from the method's own run (the label-recording clip of
+ * votess_clip_cells with a 64-long list: its status and kneeded outputs):
+ * labels[i] = least b with votess_buckets[b] >= kneeded[i], or the largest
+ * bucket (6) when status[i] is not CERTIFIED or the cell needed more than 64.
+ * [n] device buffers; enqueued on `stream`. */
+VOTESS_API votess_status votess_kmodel_labels(votess_ctx* ctx, const uint8_t* status, const int32_t* kneeded,
+                                              int64_t n, uint8_t* labels, void* stream);
+
+/* Feature standardisation fitted on the device: mean and population
+ * standard deviation (plus 1e-6) of each of the 12 features over feats
+ * [n,12], summed in double in a fixed order (deterministic).  Sets the
+ * model's mean/std; synchronises `stream`. */
+VOTESS_API votess_status votess_kmodel_fit_norm(votess_kmodel* m, const float* feats, int64_t n, void* stream);
+
+/* Versioned k-model blob (host memory): a header (magic "VTKM", version,
+ * network shape, bucket sizes, tau), the 5447 FP32 parameters, mean[12],
+ * std[12] and an FNV-1a checksum.  votess_kmodel_save writes it to blob_h
+ * (cap bytes; *len_h = votess_kmodel_blob_size(); blob_h NULL only reports
+ * the size, too small a cap is ECAPACITY) and synchronises the device.
+ * votess_kmodel_load checks magic, version, shape, buckets and checksum
+ * (EINVAL otherwise), creates a model on ctx holding those parameters (Adam
+ * state zero) into *out_h, and returns the saved tau in *tau_h (nullable). */
+VOTESS_API size_t votess_kmodel_blob_size(void);
+VOTESS_API votess_status votess_kmodel_save(votess_kmodel* m, double tau, void* blob_h, size_t cap, size_t* len_h);
+VOTESS_API votess_status votess_kmodel_load(votess_ctx* ctx, const void* blob_h, size_t len, votess_kmodel** out_h,
+                                            double* tau_h);
 
 #ifdef __cplusplus
 }

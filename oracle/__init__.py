@@ -8,6 +8,7 @@ code with the HIP path.
   lists, face areas, vertices) from the C++ file ``voronoi_oracle.cpp``;
 * :func:`kneeded`    -- the least neighbour-list size k at which the method
   certifies each cell, and the method's work at a given k;
+* :func:`labels`     -- the list-size bucket a cell's k_needed maps to;
 * ``oracle.mlp``     -- FP64 forward/backward of the k-bucket network;
 * ``oracle.features``-- the network's 12 input features from their definition.
 """
@@ -53,11 +54,13 @@ def _load():
         lib.orc_nvert.restype = i64
         lib.orc_fetch.argtypes = [P] * 11
         lib.orc_fetch.restype = None
+        lib.orc_fetch_vol_ld.argtypes = [P, P]
+        lib.orc_fetch_vol_ld.restype = None
         lib.orc_fetch_centroid.argtypes = [P, P]
         lib.orc_fetch_centroid.restype = None
         lib.orc_free.argtypes = [P]
         lib.orc_free.restype = None
-        lib.orc_kneeded.argtypes = [P, i64, P, P, P, i64, i64, i64, ctypes.c_int, P, P, P, P]
+        lib.orc_kneeded.argtypes = [P, i64, P, P, P, i64, i64, i64, ctypes.c_int, P, P, P, P, P]
         lib.orc_kneeded.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -76,7 +79,7 @@ class OracleError(ValueError):
 
 
 def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False, vertices=False,
-               threads=0, cells=None) -> dict:
+               threads=0, cells=None, volume_ld=False) -> dict:
     """Exact cells of every point (rows in input order, neighbours ascending).
 
     With ``cells`` (indices), only those rows are computed; the other rows are
@@ -86,14 +89,17 @@ def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False,
     the stopping lemma.  Returns a dict with ``row_ptr, col, area, volume,
     centroid [n,3], work [n,4] (tested, cuts, evals, created), euler`` and,
     with ``vertices``,
-    ``vrow_ptr, vxyz [nv,3], vplanes [nv,3], vdeg``.
+    ``vrow_ptr, vxyz [nv,3], vplanes [nv,3], vdeg``.  With ``volume_ld`` also
+    ``volume_ld``: each cell's volume in long double from its vertices re-solved
+    from their planes (free of the box-scale rounding the primal clip leaves
+    in small cells).
     """
     lib = _load()
     P = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
     n = P.shape[0]
     lo_, hi_ = _box(lo, hi)
     h = ctypes.c_void_p()
-    flags = (1 if all_planes else 0) | (2 if vertices else 0)
+    flags = (1 if all_planes else 0) | (2 if vertices else 0) | (4 if volume_ld else 0)
     c = None if cells is None else np.ascontiguousarray(cells, dtype=np.int64)
     rc = lib.orc_tessellate(_ptr(P), n, _ptr(lo_), _ptr(hi_), _ptr(c), 0 if c is None else c.shape[0], flags,
                             threads, ctypes.byref(h))
@@ -114,6 +120,9 @@ def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False,
                       _ptr(out["work"]), _ptr(out["euler"]), _ptr(g("vrow_ptr")), _ptr(g("vxyz")),
                       _ptr(g("vplanes")), _ptr(g("vdeg")))
         lib.orc_fetch_centroid(h, _ptr(out["centroid"]))
+        if volume_ld:
+            out["volume_ld"] = np.zeros(n, np.float64)
+            lib.orc_fetch_vol_ld(h, _ptr(out["volume_ld"]))
     finally:
         lib.orc_free(h)
     return out
@@ -123,7 +132,8 @@ def kneeded(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), cells=None, kcap=64,
     """Least certifying list size per cell (``kcap+1`` = more than kcap).
 
     With ``kwork > 0`` also returns the method's work at list size ``kwork``:
-    planes tested, vertex evaluations and vertices created per cell.
+    planes tested, vertex evaluations, vertices created and vertex norms
+    evaluated to update R^2 after cuts (``r2upd``), per cell.
     """
     lib = _load()
     P = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
@@ -135,11 +145,30 @@ def kneeded(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), cells=None, kcap=64,
     tested = np.zeros(nc, np.int64)
     evals = np.zeros(nc, np.int64)
     created = np.zeros(nc, np.int64)
+    r2upd = np.zeros(nc, np.int64)
     rc = lib.orc_kneeded(_ptr(P), n, _ptr(lo_), _ptr(hi_), _ptr(c), nc, kcap, kwork, threads, _ptr(kn),
-                         _ptr(tested), _ptr(evals), _ptr(created))
+                         _ptr(tested), _ptr(evals), _ptr(created), _ptr(r2upd))
     if rc:
         raise OracleError(ERRORS.get(rc, str(rc)))
-    return dict(kneeded=kn, tested=tested, evals=evals, created=created)
+    return dict(kneeded=kn, tested=tested, evals=evals, created=created, r2upd=r2upd)
+
+
+BUCKETS = (8, 12, 16, 24, 32, 48, 64)
+
+
+def labels(kneeded) -> np.ndarray:
+    """Training label of each cell (the least list-size bucket that
+    certifies it): the first b with BUCKETS[b] >= k_needed, or the largest
+    bucket when the cell needs more than the largest bucket."""
+    out = []
+    for kn in np.asarray(kneeded).tolist():
+        b = len(BUCKETS) - 1
+        for i, k in enumerate(BUCKETS):
+            if k >= kn:
+                b = i
+                break
+        out.append(b)
+    return np.array(out, dtype=np.uint8)
 
 
 def rows(res: dict):

@@ -6,7 +6,7 @@
 //
 // What it computes (paper, Summary section): the Voronoi cell of every
 // generator, built by clipping a bounding box with the perpendicular bisectors
-// between the generator and its neighbours, with a "security radius" test that
+// between the generator and its neighbours, with a security-radius test that
 // proves the cell complete; outputs are cell geometry and natural-neighbour
 // lists (Features section).  The security-radius lemma is the one of the cited
 // method (Ray et al. 2018, "Meshless Voronoi on the GPU"): if every vertex of
@@ -54,6 +54,7 @@ struct Work {            // counts of the method's elementary operations
   int64_t cuts = 0;      // planes that removed at least one vertex
   int64_t evals = 0;     // vertex-versus-plane evaluations
   int64_t created = 0;   // vertices created by cuts
+  int64_t r2 = 0;        // vertex norms evaluated to update R^2 after cuts
 };
 
 struct Poly {
@@ -194,7 +195,68 @@ struct Poly {
 };
 
 // ---------------------------------------------------------------------------
-// The oracle's own uniform grid (about 4 points per grid cell).
+// Volume of a finished cell in long double (64-bit mantissa on x86) from its
+// combinatorics alone: every vertex is re-solved from three of the planes it
+// lies on (Cramer's rule, seed-relative, exact plane data: n = q - p is exact
+// for double inputs), and the faces' vertex cycles are fanned from their
+// first vertex.  The primal clip interpolates new vertices between vertices
+// at the box's scale, so on cells far smaller than the box its double
+// vertices carry errors of order u times the box size; this volume has no
+// such error and is the reference the FP64 volume bar uses.
+using LD = long double;
+struct V3L {
+  LD x, y, z;
+};
+inline V3L crossL(const V3L& a, const V3L& b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline LD dotL(const V3L& a, const V3L& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// plane id >= 0: bisector with point id; -1..-6: walls x-, x+, y-, y+, z-, z+
+inline void planeL(int64_t id, const double* P, int64_t i, const double* lo, const double* hi, V3L& n, LD& c) {
+  if (id >= 0) {
+    n = {(LD)P[3 * id] - (LD)P[3 * i], (LD)P[3 * id + 1] - (LD)P[3 * i + 1], (LD)P[3 * id + 2] - (LD)P[3 * i + 2]};
+    c = dotL(n, n) / 2;
+  } else {
+    const int w = (int)(-id - 1), ax = w >> 1;
+    const bool up = w & 1;
+    n = {0, 0, 0};
+    (ax == 0 ? n.x : ax == 1 ? n.y : n.z) = up ? 1 : -1;
+    c = up ? (LD)hi[ax] - (LD)P[3 * i + ax] : (LD)P[3 * i + ax] - (LD)lo[ax];
+  }
+}
+
+double volume_ld(const Poly& C, const double* P, int64_t i, const double* lo, const double* hi) {
+  const size_t nv = C.v.size();
+  std::vector<std::vector<int64_t>> inc(nv);
+  for (size_t k = 0; k < C.f.size(); ++k)
+    for (int x : C.f[k]) inc[x].push_back(C.fid[k]);
+  std::vector<V3L> w(nv);
+  for (size_t x = 0; x < nv; ++x) {
+    auto& s = inc[x];
+    std::sort(s.begin(), s.end());
+    s.erase(std::unique(s.begin(), s.end()), s.end());
+    w[x] = {(LD)C.v[x][0], (LD)C.v[x][1], (LD)C.v[x][2]};
+    if (s.size() < 3) continue;
+    V3L na, nb, nc;
+    LD ca, cb, cc;
+    planeL(s[0], P, i, lo, hi, na, ca);
+    planeL(s[1], P, i, lo, hi, nb, cb);
+    planeL(s[2], P, i, lo, hi, nc, cc);
+    const V3L bc = crossL(nb, nc), ca_ = crossL(nc, na), ab = crossL(na, nb);
+    const LD det = dotL(na, bc);
+    if (det == 0) continue;
+    w[x] = {(ca * bc.x + cb * ca_.x + cc * ab.x) / det, (ca * bc.y + cb * ca_.y + cc * ab.y) / det,
+            (ca * bc.z + cb * ca_.z + cc * ab.z) / det};
+  }
+  LD vol = 0;
+  for (const auto& cyc : C.f)
+    for (size_t k = 1; k + 1 < cyc.size(); ++k) vol += dotL(w[cyc[0]], crossL(w[cyc[k]], w[cyc[k + 1]]));
+  return (double)(vol / 6);
+}
+
+// ---------------------------------------------------------------------------
+// The oracle's own uniform grid (about four points per grid cell).
 struct Grid {
   int g[3];
   double lo[3], hi[3], h[3];
@@ -379,6 +441,7 @@ struct Result {
   std::vector<int32_t> col;
   std::vector<double> area;  // face area per (row, col) entry
   std::vector<double> vol;
+  std::vector<double> vol_ld;  // [n] volume_ld() (flag 4), else empty
   std::vector<double> cen;   // [n,3] cell centroids (absolute)
   std::vector<int64_t> vrow_ptr;
   std::vector<double> vxyz;
@@ -396,7 +459,8 @@ typedef struct Result orc_result;
 
 // Computes every cell, or only the cells listed in `cells` (others are left
 // empty).  flags: 1 = clip by all other points (no certificate), 2 = keep
-// vertices.  Returns 0, or 1 bad box, 2 point outside box, 3 duplicate.
+// vertices, 4 = also the long-double volume of each cell.  Returns 0, or 1
+// bad box, 2 point outside box, 3 duplicate.
 int orc_tessellate(const double* P, int64_t n, const double* lo, const double* hi, const int64_t* cells, int64_t nc,
                    int flags, int nthreads, orc_result** out) {
   *out = nullptr;
@@ -404,7 +468,7 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
   if (bad) return bad;
   Grid G;
   G.build(P, n, lo, hi);
-  const bool all = flags & 1, keepv = flags & 2;
+  const bool all = flags & 1, keepv = flags & 2, want_ld = flags & 4;
   std::vector<std::vector<int32_t>> nb(n);
   std::vector<std::vector<double>> ar(n);
   std::vector<std::vector<double>> vx(keepv ? n : 0);
@@ -412,6 +476,7 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
   Result* res = new Result;
   res->n = n;
   res->vol.assign(n, 0.0);
+  if (want_ld) res->vol_ld.assign(n, 0.0);
   res->cen.assign(3 * n, 0.0);
   res->work.assign(4 * n, 0);
   res->euler.assign(n, 0);
@@ -425,6 +490,7 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
     Work w;
     exact_cell(G, P, n, lo, hi, i, all, C, w);
     res->vol[i] = C.volume();
+    if (want_ld) res->vol_ld[i] = volume_ld(C, P, i, lo, hi);
     const V3 mom = C.moment();
     for (int a = 0; a < 3; ++a) res->cen[3 * i + a] = P[3 * i + a] + (res->vol[i] > 0.0 ? mom[a] / res->vol[i] : 0.0);
     res->work[4 * i + 0] = w.tested;
@@ -499,6 +565,11 @@ void orc_fetch(const orc_result* r, int64_t* row_ptr, int32_t* col, double* area
   cp(vdeg, r->vdeg.data(), r->vdeg.size() * sizeof(int32_t));
 }
 
+// Long-double volumes [n] (flag 4 only; zero for rows not computed).
+void orc_fetch_vol_ld(const orc_result* r, double* v) {
+  if (v && !r->vol_ld.empty()) std::memcpy(v, r->vol_ld.data(), r->vol_ld.size() * sizeof(double));
+}
+
 // Cell centroids [n,3] (zero for rows not computed).
 void orc_fetch_centroid(const orc_result* r, double* cen) {
   if (cen && !r->cen.empty()) std::memcpy(cen, r->cen.data(), r->cen.size() * sizeof(double));
@@ -513,13 +584,14 @@ void orc_free(orc_result* r) { delete r; }
 // vertex radius after clipping by q_1..q_m, or iff the list holds all n-1 other
 // points.  Outputs per cell:
 //   kneeded[c]  least list size that certifies (capped: kcap+1 means "more"),
-//   tested/evals/created[c]  work of the method at list size `kwork`
+//   tested/evals/created/r2upd[c]  work of the method at list size `kwork`
 //                (planes tested before the early stop, vertex evaluations,
-//                vertices created); pass kwork <= 0 to skip.
+//                vertices created, vertex norms evaluated to update R^2 after
+//                each cut); pass kwork <= 0 to skip.
 // Returns 0 or a validation code as orc_tessellate.
 int orc_kneeded(const double* P, int64_t n, const double* lo, const double* hi, const int64_t* cells, int64_t nc,
                 int64_t kcap, int64_t kwork, int nthreads, int32_t* kneeded, int64_t* tested, int64_t* evals,
-                int64_t* created) {
+                int64_t* created, int64_t* r2upd) {
   const int bad = validate(P, n, lo, hi);
   if (bad) return bad;
   Grid G;
@@ -549,7 +621,10 @@ int orc_kneeded(const double* P, int64_t n, const double* lo, const double* hi, 
       }
       const bool in_k = (kwork > 0 && m <= kwork);
       Work& ww = in_k ? wk : w;
-      if (C.clip(S.R.normal(e.second), 0.5 * e.first, e.second, ww)) r2 = C.radius2();
+      if (C.clip(S.R.normal(e.second), 0.5 * e.first, e.second, ww)) {
+        r2 = C.radius2();
+        ww.r2 += (int64_t)C.v.size();
+      }
       fprev = e.first > 4.0 * r2;  // F_m
       if (fprev && kn < 0) kn = m;
     }
@@ -559,6 +634,7 @@ int orc_kneeded(const double* P, int64_t n, const double* lo, const double* hi, 
     if (tested) tested[t] = wk.tested;
     if (evals) evals[t] = wk.evals;
     if (created) created[t] = wk.created;
+    if (r2upd) r2upd[t] = wk.r2;
   }
   return 0;
 }

@@ -49,12 +49,13 @@ class Stats(C.Structure):
                 ("refined_cells", C.c_int64), ("streamed_cells", C.c_int64), ("bucket_cells", C.c_int64 * 8),
                 ("ms_sort", C.c_double), ("ms_knn", C.c_double), ("ms_clip", C.c_double),
                 ("ms_features", C.c_double), ("ms_mlp", C.c_double), ("ms_assemble", C.c_double),
-                ("ms_fallback", C.c_double), ("ms_total", C.c_double)]
+                ("ms_fallback", C.c_double), ("ms_total", C.c_double),
+                ("pass_streamed", C.c_int64 * MAX_PASSES)]
 
     def as_dict(self) -> dict:
         n = self.npasses
-        return dict(passes=[dict(k=self.pass_k[i], cells=self.pass_cells[i], failed=self.pass_failed[i])
-                            for i in range(n)],
+        return dict(passes=[dict(k=self.pass_k[i], cells=self.pass_cells[i], failed=self.pass_failed[i],
+                                 streamed=self.pass_streamed[i]) for i in range(n)],
                     capacity_cells=self.capacity_cells, fallback_cells=self.fallback_cells,
                     unresolved_cells=self.unresolved_cells, rechecks=self.rechecks,
                     refined_cells=self.refined_cells, streamed_cells=self.streamed_cells, bucket_cells=list(self.bucket_cells)[:NBUCKET],
@@ -102,6 +103,11 @@ SIGNATURES = {
     "votess_kmodel_grad": (C.c_int, [P, P, P, i64, P, P, P]),
     "votess_kmodel_train_step": (C.c_int, [P, P, P, i64, C.c_float, P, P]),
     "votess_kmodel_choose": (C.c_int, [P, P, i64, C.c_float, P, P]),
+    "votess_kmodel_labels": (C.c_int, [P, P, P, i64, P, P]),
+    "votess_kmodel_fit_norm": (C.c_int, [P, P, i64, P]),
+    "votess_kmodel_blob_size": (C.c_size_t, []),
+    "votess_kmodel_save": (C.c_int, [P, C.c_double, P, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "votess_kmodel_load": (C.c_int, [P, P, C.c_size_t, C.POINTER(P), C.POINTER(C.c_double)]),
 }
 DATA_SYMBOLS = ["votess_buckets"]
 

@@ -495,6 +495,15 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   int nretry = 0;
   for (int kk = k_first; nretry < P.max_gpu_retries && kk < kMaxK; ++nretry) kk = std::min(2 * kk, kMaxK);
 
+  // cells that entered the stream phase so far (device counter 5)
+  auto stream_entries = [&](int64_t& out_v) -> votess_status {
+    unsigned long long v = 0;
+    VT_HIP(hipMemcpyAsync(&v, counters.get<unsigned long long>() + 5, 8, hipMemcpyDeviceToHost, st));
+    VT_HIP(hipStreamSynchronize(st));
+    out_v = (int64_t)v;
+    return VOTESS_OK;
+  };
+  int64_t entered = 0, entered_before = 0;
   // ---- first pass over all cells
   int k = P.k0;
   int nfail = 0;
@@ -536,7 +545,13 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
                                  (1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY), ctx->ws, st));
     VT_HIP(hipMemcpyAsync(&nfail, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
     VT_HIP(hipStreamSynchronize(st));
-    if (!P.kmodel && S.npasses < VOTESS_MAX_PASSES) S.pass_failed[S.npasses++] = nfail;
+    if (!P.kmodel && S.npasses < VOTESS_MAX_PASSES) {
+      VT_TRY(stream_entries(entered));
+      S.pass_streamed[S.npasses] = entered - entered_before;
+      entered_before = entered;
+      S.pass_failed[S.npasses++] = nfail;
+    }
+    if (P.kmodel) VT_TRY(stream_entries(entered_before));
   }
   // ---- GPU retry ladder: cells whose radius test failed retry at doubled k;
   // cells that overflowed the fast kernel rerun in the large-capacity kernel
@@ -590,8 +605,11 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     VT_HIP(hipMemcpyAsync(&nfail, ctx->d_counter, 4, hipMemcpyDeviceToHost, st));
     VT_HIP(hipStreamSynchronize(st));
     if (S.npasses < VOTESS_MAX_PASSES) {
+      VT_TRY(stream_entries(entered));
       S.pass_k[S.npasses] = k;
       S.pass_cells[S.npasses] = cells_in;
+      S.pass_streamed[S.npasses] = entered - entered_before;
+      entered_before = entered;
       S.pass_failed[S.npasses++] = nfail;
     }
     std::swap(cur, nxt);

@@ -1,6 +1,6 @@
 // Retry compaction (cells whose certificate failed, in order) and output assembly: the
-// per-cell neighbour lists become one CSR "jagged array" of neighbour indices
-// (paper, Features section), rows in original input order by default or in
+// per-cell neighbour lists become one CSR array of rows of neighbour indices
+// (paper, Features section: a jagged array of natural neighbours), rows in original input order by default or in
 // grid-sorted order, each row ascending; volumes, face areas, centroids and
 // vertices follow.
 #include "internal.h"

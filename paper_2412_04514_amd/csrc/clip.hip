@@ -1,8 +1,8 @@
-// Cell clipping with the security-radius certificate (paper, Summary: each
-// cell is computed "by iteratively clipping a bounding box using the
-// perpendicular bisectors between the point and its nearby neighbors", and a
-// "security radius" condition proves it valid; the radius lemma is the one of
-// Ray et al. 2018, cited by the paper).
+// Cell clipping with the security-radius certificate (paper, Summary section:
+// each cell starts as a bounding box that is cut, one neighbour at a time, by
+// the bisector plane between the generator and that neighbour, and a
+// security-radius condition proves the result complete; the radius lemma is
+// the one of Ray et al. 2018, cited by the paper).
 //
 // MI355X design
 //  * A group of L lanes owns one cell; a 64-lane wave (= one workgroup) holds
@@ -676,6 +676,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     const int ik0 = (have && st == VOTESS_CELL_RADIUS) ? a.knn[(size_t)t_idx * a.k + a.k - 1] : -1;
     const bool strm = ik0 >= 0;  // a full list that did not certify
     if (strm) st = ST_RUN;
+    if (strm && j == 0 && a.counters) atomicAdd(&a.counters[5], 1ull);
     const GridDev& Gd = a.grid;
     const int cx = axis_cell(p64x, Gd.lo0, Gd.ih0, Gd.g0);
     const int cy = axis_cell(p64y, Gd.lo1, Gd.ih1, Gd.g1);
@@ -696,7 +697,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       for (int t = j; t < H; t += L) {
         if (tri[vb + t] == kEmpty) continue;
         const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
-        const double rad = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-6) + (RECHECK ? 2.0 * (double)verr[vb + t] : 0.0);
+        // verr bounds each coordinate of the float vertex, so the true ball's
+        // centre lies within verr per axis (a box of half-width verr) and its
+        // radius within sqrt(3) verr: widening by 4 verr > (1 + sqrt(3)) verr
+        // covers both
+        const double rad = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-6) + (RECHECK ? 4.0 * (double)verr[vb + t] : 0.0);
         mn0 = fmin(mn0, X - rad); mx0 = fmax(mx0, X + rad);
         mn1 = fmin(mn1, Y - rad); mx1 = fmax(mx1, Y + rad);
         mn2 = fmin(mn2, Z - rad); mx2 = fmax(mx2, Z + rad);

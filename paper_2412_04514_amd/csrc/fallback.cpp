@@ -1,6 +1,5 @@
-// Host fallback for cells the GPU passes could not certify (paper, Summary:
-// "If a cell cannot be validated, an automatic CPU fallback mechanism ensures
-// robustness").  Each cell is clipped with no bound on the neighbour count:
+// Host fallback for cells the GPU passes could not certify (paper, Summary
+// section: cells that fail validation are recomputed on the CPU).  Each cell is clipped with no bound on the neighbour count:
 // grid rings around the seed are consumed in order, each ring's points nearest
 // first, until the scanned block provably contains every point within 2R of
 // the seed (R = farthest vertex).  The polyhedron uses the same dual form as

@@ -1,5 +1,5 @@
-// Grid sort of the generators (paper, Summary: "the input set of points is
-// sorted into a grid") as a counting sort:
+// Grid sort of the generators (paper, Summary section: the points are first
+// binned into a uniform grid) as a counting sort:
 //   a1  cell id of every point + atomic histogram (the atomic's return value is
 //       the point's provisional rank inside its cell);
 //   a2  exclusive scan of the histogram -> cell_start;

@@ -129,7 +129,8 @@ struct ClipLaunch {
   int32_t* vplanes;
   double* area = nullptr;        // [rows, max_nbr] face areas next to nbr (nullable)
   double* centroid = nullptr;    // [rows, 3] cell centroids (nullable)
-  unsigned long long* counters;  // [8]: rechecks, unresolved, capacity, refined, streamed -- nullable
+  unsigned long long* counters;  // [8]: rechecks, unresolved, capacity, refined, streamed (certified by the
+                                 // stream phase), stream entries -- nullable
   int stream = 0;                // 1: uncertified cells continue by grid rings
   const int32_t* cell_start = nullptr;
   GridDev grid{};

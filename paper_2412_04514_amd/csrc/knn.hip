@@ -1,5 +1,5 @@
-// k-nearest-neighbour search over the grid (paper, Summary: after the grid
-// sort "a k-nearest neighbors search is performed").
+// k-nearest-neighbour search over the grid (paper, Summary section: the
+// neighbour search that follows the grid sort).
 //
 // A group of G lanes serves one query (queries in grid-sorted order, so that
 // neighbouring groups scan overlapping grid cells), in two phases:

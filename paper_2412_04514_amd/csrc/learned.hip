@@ -21,6 +21,7 @@
 #include "device_common.h"
 
 #include <cfloat>
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -30,6 +31,7 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NF, OFF_W2 = OFF_B1 + NH, OFF_B
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NO * NH, NPARAM = OFF_B3 + NO;
 static_assert(NPARAM == VOTESS_NPARAM, "parameter layout");
 constexpr int kSamplesPerBlock = 64;  // four 16-sample tiles per wave
+__device__ constexpr int kBuckets[VOTESS_NBUCKET] = {8, 12, 16, 24, 32, 48, 64};
 }  // namespace votess
 
 struct votess_kmodel {
@@ -464,6 +466,59 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
   theta[p] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
+// Training label of a cell from the method's own run (status and k_needed of
+// the label-recording clip): the least bucket b with buckets[b] >= k_needed,
+// or the largest bucket when the cell was not certified by its list or
+// needed more than the largest bucket.
+__global__ void k_labels(const uint8_t* __restrict__ status, const int* __restrict__ kneeded, int n,
+                         uint8_t* __restrict__ labels) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int kn = status[i] == VOTESS_CELL_CERTIFIED ? kneeded[i] : INT_MAX;
+  int b = 0;
+  while (b < NO - 1 && kBuckets[b] < kn) ++b;
+  labels[i] = (uint8_t)b;
+}
+
+// Standardisation statistics, deterministic: each block sums x and x^2 of
+// every feature in double over a fixed strided range (a fixed-order tree in
+// LDS), then one block adds the partials in block order.
+constexpr int kNormBlocks = 256;
+__global__ __launch_bounds__(256) void k_norm_partial(const float* __restrict__ feats, int n,
+                                                      double* __restrict__ partial) {
+  __shared__ double red[256];
+  for (int f = 0; f < 2 * NF; ++f) {
+    double acc = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+      const double x = feats[(size_t)i * NF + (f % NF)];
+      acc += f < NF ? x : x * x;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 2 * NF + f] = red[0];
+    __syncthreads();
+  }
+}
+
+// mean = S1 / n, std = sqrt(max(S2 / n - mean^2, 0)) + 1e-6 (population std)
+__global__ void k_norm_final(const double* __restrict__ partial, int blocks, int n, float* __restrict__ norm) {
+  const int f = threadIdx.x;
+  if (f >= NF) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = 0; b < blocks; ++b) {
+    s1 += partial[(size_t)b * 2 * NF + f];
+    s2 += partial[(size_t)b * 2 * NF + NF + f];
+  }
+  const double mean = s1 / n;
+  const double var = fmax(s2 / n - mean * mean, 0.0);
+  norm[f] = (float)mean;
+  norm[NF + f] = (float)(sqrt(var) + 1e-6);
+}
+
 }  // namespace
 
 votess_status run_features(votess_ctx* ctx, const void* sorted, votess_dtype dt, int n, const GridDev& G,
@@ -561,6 +616,13 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
   S.ms_features += ms;
   (void)hipEventElapsedTime(&ms, e1, e2);
   S.ms_mlp += ms;
+  int64_t entered_prev = 0;
+  if (base.counters) {
+    unsigned long long e = 0;
+    if (hipMemcpyAsync(&e, base.counters + 5, 8, hipMemcpyDeviceToHost, st) == hipSuccess &&
+        hipStreamSynchronize(st) == hipSuccess)
+      entered_prev = (int64_t)e;
+  }
   for (int b = 0; b < NO && rc == VOTESS_OK; ++b) {
     int cnt = 0;
     // the compaction takes a status mask; bucket values are 0..6, so bit b selects bucket b
@@ -592,12 +654,28 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
     S.ms_knn += ms;
     (void)hipEventElapsedTime(&ms, e1, e2);
     S.ms_clip += ms;
+    if (rc != VOTESS_OK) break;
+    // cells of this bucket still uncertified after the pass, and cells its
+    // lists left uncertified that went on into the stream phase
+    int nfail = 0;
+    unsigned long long entered = 0;
+    rc = launch_compact_failed(base.status, cells_buf, cnt, (int32_t*)knnb, ctx->d_counter,
+                               (uint8_t)((1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY)), ctx->ws, st);
+    if (rc != VOTESS_OK) break;
+    if (hipMemcpyAsync(&nfail, ctx->d_counter, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        (base.counters && hipMemcpyAsync(&entered, base.counters + 5, 8, hipMemcpyDeviceToHost, st) != hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(VOTESS_EHIP, "learned pass: failure count");
+      break;
+    }
     if (S.npasses < VOTESS_MAX_PASSES) {
       S.pass_k[S.npasses] = k;
       S.pass_cells[S.npasses] = cnt;
-      S.pass_failed[S.npasses] = 0;
+      S.pass_failed[S.npasses] = nfail;
+      S.pass_streamed[S.npasses] = (int64_t)entered - entered_prev;
       S.npasses++;
     }
+    entered_prev = (int64_t)entered;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -764,6 +842,113 @@ votess_status votess_kmodel_train_step(votess_kmodel* km, const float* feats, co
   k_adam<<<(NPARAM + 255) / 256, 256, 0, st>>>(km->theta, km->m, km->v, km->grads, lr, c1, c2);
   VT_HIP(hipGetLastError());
   if (loss) VT_HIP(hipMemcpyAsync(loss, km->grads + NPARAM, 4, hipMemcpyDeviceToDevice, st));
+  return VOTESS_OK;
+}
+
+
+/* ---- versioned blob: the weights, the standardisation and tau ---------- */
+namespace {
+constexpr uint32_t kBlobMagic = 0x4D4B5456u;  // "VTKM"
+constexpr uint32_t kBlobVersion = 1;
+struct BlobHead {
+  uint32_t magic, version, nfeat, nhid, nbucket, nparam;
+  int32_t buckets[VOTESS_NBUCKET];
+  uint32_t pad;
+  double tau;
+};
+constexpr size_t kBlobBytes = sizeof(BlobHead) + (size_t)(NPARAM + 2 * NF) * 4 + 8;
+uint64_t fnv1a(const unsigned char* p, size_t len) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < len; ++i) h = (h ^ p[i]) * 0x100000001b3ull;
+  return h;
+}
+}  // namespace
+
+size_t votess_kmodel_blob_size(void) { return kBlobBytes; }
+
+votess_status votess_kmodel_save(votess_kmodel* km, double tau, void* blob_h, size_t cap, size_t* len_h) {
+  if (!km) return fail(VOTESS_EINVAL, "kmodel_save: null model");
+  if (len_h) *len_h = kBlobBytes;
+  if (!blob_h) return VOTESS_OK;
+  if (cap < kBlobBytes) return fail(VOTESS_ECAPACITY, "kmodel_save: blob needs %zu bytes, got %zu", kBlobBytes, cap);
+  if (!(tau > 0.0 && tau <= 1.0)) return fail(VOTESS_EINVAL, "kmodel_save: tau must be in (0, 1]");
+  std::vector<unsigned char> buf(kBlobBytes, 0);
+  BlobHead h{};
+  h.magic = kBlobMagic;
+  h.version = kBlobVersion;
+  h.nfeat = NF;
+  h.nhid = NH;
+  h.nbucket = NO;
+  h.nparam = NPARAM;
+  for (int b = 0; b < NO; ++b) h.buckets[b] = votess_buckets[b];
+  h.tau = tau;
+  std::memcpy(buf.data(), &h, sizeof(h));
+  float* body = (float*)(buf.data() + sizeof(h));
+  VT_TRY(votess_kmodel_get_params(km, body, body + NPARAM, body + NPARAM + NF));
+  const uint64_t sum = fnv1a(buf.data(), kBlobBytes - 8);
+  std::memcpy(buf.data() + kBlobBytes - 8, &sum, 8);
+  std::memcpy(blob_h, buf.data(), kBlobBytes);
+  return VOTESS_OK;
+}
+
+votess_status votess_kmodel_load(votess_ctx* ctx, const void* blob_h, size_t len, votess_kmodel** out_h,
+                                 double* tau_h) {
+  if (!ctx || !blob_h || !out_h) return fail(VOTESS_EINVAL, "kmodel_load: null argument");
+  *out_h = nullptr;
+  if (len != kBlobBytes) return fail(VOTESS_EINVAL, "kmodel_load: blob of %zu bytes, expected %zu", len, kBlobBytes);
+  const unsigned char* b = (const unsigned char*)blob_h;
+  BlobHead h;
+  std::memcpy(&h, b, sizeof(h));
+  if (h.magic != kBlobMagic) return fail(VOTESS_EINVAL, "kmodel_load: not a k-model blob");
+  if (h.version != kBlobVersion) return fail(VOTESS_EINVAL, "kmodel_load: blob version %u, expected %u", h.version, kBlobVersion);
+  if (h.nfeat != (uint32_t)NF || h.nhid != (uint32_t)NH || h.nbucket != (uint32_t)NO || h.nparam != (uint32_t)NPARAM)
+    return fail(VOTESS_EINVAL, "kmodel_load: network shape differs from this library's");
+  for (int i = 0; i < NO; ++i)
+    if (h.buckets[i] != votess_buckets[i]) return fail(VOTESS_EINVAL, "kmodel_load: bucket sizes differ");
+  uint64_t sum;
+  std::memcpy(&sum, b + kBlobBytes - 8, 8);
+  if (sum != fnv1a(b, kBlobBytes - 8)) return fail(VOTESS_EINVAL, "kmodel_load: checksum mismatch");
+  if (!(h.tau > 0.0 && h.tau <= 1.0)) return fail(VOTESS_EINVAL, "kmodel_load: bad tau");
+  std::vector<float> body(NPARAM + 2 * NF);
+  std::memcpy(body.data(), b + sizeof(h), body.size() * 4);
+  votess_kmodel* km = votess_kmodel_create(ctx, 0);
+  if (!km) return VOTESS_ENOMEM;
+  const votess_status rc = votess_kmodel_set_params(km, body.data(), body.data() + NPARAM, body.data() + NPARAM + NF);
+  if (rc != VOTESS_OK) {
+    votess_kmodel_destroy(km);
+    return rc;
+  }
+  *out_h = km;
+  if (tau_h) *tau_h = h.tau;
+  return VOTESS_OK;
+}
+
+votess_status votess_kmodel_labels(votess_ctx* ctx, const uint8_t* status, const int32_t* kneeded, int64_t n,
+                                   uint8_t* labels, void* stream) {
+  if (!ctx) return fail(VOTESS_EINVAL, "kmodel_labels: null ctx");
+  if (n < 0 || n >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "kmodel_labels: bad size");
+  if (n > 0 && (!status || !kneeded || !labels)) return fail(VOTESS_EINVAL, "kmodel_labels: null buffer");
+  if (n == 0) return VOTESS_OK;
+  VT_HIP(hipSetDevice(ctx->device));
+  k_labels<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(status, kneeded, (int)n, labels);
+  VT_HIP(hipGetLastError());
+  return VOTESS_OK;
+}
+
+votess_status votess_kmodel_fit_norm(votess_kmodel* km, const float* feats, int64_t n, void* stream) {
+  if (!km) return fail(VOTESS_EINVAL, "kmodel_fit_norm: null model");
+  if (n < 1 || n >= (1LL << 31) - 1 || !feats) return fail(VOTESS_EINVAL, "kmodel_fit_norm: bad features");
+  VT_HIP(hipSetDevice(km->ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)std::min<int64_t>(kNormBlocks, (n + 255) / 256);
+  double* partial = (double*)dev_alloc(km->ctx, (size_t)blocks * 2 * NF * sizeof(double));
+  if (!partial) return fail(VOTESS_ENOMEM, "kmodel_fit_norm: partial sums");
+  k_norm_partial<<<blocks, 256, 0, st>>>(feats, (int)n, partial);
+  k_norm_final<<<1, 64, 0, st>>>(partial, blocks, (int)n, km->norm);
+  const hipError_t e1 = hipGetLastError();
+  const hipError_t e2 = hipStreamSynchronize(st);
+  dev_free(km->ctx, partial);
+  if (e1 != hipSuccess || e2 != hipSuccess) return fail(VOTESS_EHIP, "kmodel_fit_norm: kernels failed");
   return VOTESS_OK;
 }
 

@@ -33,16 +33,38 @@ def _stream():
 
 
 class KModel:
-    def __init__(self, ctx=None, seed: int = 0, tau: float = 0.9):
+    def __init__(self, ctx=None, seed: int = 0, tau: float = 0.9, _handle=None):
         from . import Context
         self.ctx = ctx or Context.get()
         self.lib = self.ctx.lib
-        h = self.lib.votess_kmodel_create(self.ctx.handle, seed)
+        h = _handle if _handle is not None else self.lib.votess_kmodel_create(self.ctx.handle, seed)
         if not h:
             raise _lib.VotessError(1, self.lib.votess_last_error().decode())
         self.handle = C.c_void_p(h)
         self.tau = tau
         self.history: list[float] = []
+
+    # versioned blob (weights, standardisation, tau) ------------------------
+    def save(self) -> bytes:
+        n = self.lib.votess_kmodel_blob_size()
+        buf = C.create_string_buffer(n)
+        ln = C.c_size_t(0)
+        check(self.lib.votess_kmodel_save(self.handle, float(self.tau), buf, n, C.byref(ln)))
+        return buf.raw[: ln.value]
+
+    @classmethod
+    def load(cls, blob: bytes, ctx=None) -> "KModel":
+        from . import Context
+        ctx = ctx or Context.get()
+        h = C.c_void_p()
+        tau = C.c_double(0.0)
+        check(ctx.lib.votess_kmodel_load(ctx.handle, blob, len(blob), C.byref(h), C.byref(tau)))
+        return cls(ctx=ctx, tau=tau.value, _handle=h.value)
+
+    def fit_norm(self, feats: torch.Tensor):
+        """Sets the standardisation to the mean / std of ``feats`` [n,12] (on the device)."""
+        feats = feats.contiguous()
+        check(self.lib.votess_kmodel_fit_norm(self.handle, _ptr(feats), feats.shape[0], _stream()))
 
     def __del__(self):
         try:
@@ -113,23 +135,33 @@ def features(sorted_, grid, cell_start, queries=None, ctx=None) -> torch.Tensor:
     return out[:nq]
 
 
+def labels(status: torch.Tensor, kneeded: torch.Tensor, ctx=None) -> torch.Tensor:
+    """Bucket label per cell from the label-recording clip (library kernel)."""
+    from . import Context
+    ctx = ctx or Context.get()
+    n = status.shape[0]
+    out = torch.empty(max(n, 1), dtype=torch.uint8, device=status.device)
+    check(ctx.lib.votess_kmodel_labels(ctx.handle, _ptr(status.contiguous()), _ptr(kneeded.contiguous()), n,
+                                       _ptr(out), _stream()))
+    return out[:n]
+
+
 def method_labels(sorted_, grid, cell_start, cells, precision: str = "f32"):
-    """Bucket labels from the method: least bucket >= the certifying list size."""
+    """Bucket labels from the method: least bucket >= the certifying list size
+    (the largest bucket when a 64-long list does not certify the cell)."""
     from . import clip_cells, knn
     lists = knn(sorted_, grid, cell_start, 64, queries=cells, dist="f32" if precision != "f64" else "f64")
     r = clip_cells(sorted_, lists, 64, cells=cells, precision=precision, kneeded=True)
-    st = r["status"].cpu().numpy()
-    kn = r["kneeded"].cpu().numpy()
-    cap = np.nonzero(st == 2)[0]
-    if len(cap):  # overflow of the fast kernel: same lists, large-capacity kernel
-        idx = torch.from_numpy(cap).to(cells.device)
-        rc = clip_cells(sorted_, lists[idx].contiguous(), 64, cells=cells[idx].contiguous(), precision=precision,
+    st, kn = r["status"], r["kneeded"]
+    cap = torch.nonzero(st == 2).flatten()
+    if cap.numel():  # overflow of the fast kernel: same lists, large-capacity kernel
+        rc = clip_cells(sorted_, lists[cap].contiguous(), 64, cells=cells[cap].contiguous(), precision=precision,
                         kneeded=True, capacity=1)
-        st[cap] = rc["status"].cpu().numpy()
-        kn[cap] = rc["kneeded"].cpu().numpy()
-    kn = np.where(st == 0, kn, 65)
-    lab = np.minimum(np.searchsorted(BUCKETS, kn, side="left"), 6).astype(np.uint8)
-    return lab, kn
+        st = st.clone()
+        kn = kn.clone()
+        st[cap] = rc["status"]
+        kn[cap] = rc["kneeded"]
+    return labels(st, kn), kn
 
 
 def train(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), n_train: int = 1 << 21, epochs: int = 4,
@@ -144,14 +176,11 @@ def train(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), n_train: int = 1 << 
     cells = torch.from_numpy(cells_np).to(points.device)
     X = features(srt, grid, cs, cells)
     lab, kn = method_labels(srt, grid, cs, cells, precision)
-    Xh = X.cpu().numpy().astype(np.float64)
-    mean = Xh.mean(axis=0)
-    std = Xh.std(axis=0) + 1e-6
     model = KModel(seed=seed)
-    model.set_params(mean=mean, std=std)
+    model.fit_norm(X)
     order = torch.from_numpy(rng.permutation(len(cells_np))).to(points.device)
     Xs = X[order].contiguous()
-    Ys = torch.from_numpy(lab).to(points.device)[order].contiguous()
+    Ys = lab[order].contiguous()
     nb = len(cells_np) // batch
     t1 = time.time()
     for ep in range(epochs):
@@ -165,7 +194,7 @@ def train(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), n_train: int = 1 << 
     torch.cuda.synchronize()
     model.train_seconds = time.time() - t1
     model.prep_seconds = t1 - t0
-    model.label_hist = np.bincount(lab, minlength=7).tolist()
+    model.label_hist = torch.bincount(lab.long(), minlength=7).cpu().tolist()
     return model
 
 

@@ -6,11 +6,12 @@ import sys
 import numpy as np
 
 # Parity bars.  FP64 path: neighbour sets bit-exact, volumes 1e-12 relative
-# with a floor of 1e-14 of the mean cell volume (cells orders of magnitude
-# smaller than the mean carry rounding from the box-scale start of clipping).
-# FP32 path: neighbour sets bit-exact, volumes 1e-5 relative.
+# to the oracle's long-double volume (oracle.tessellate(volume_ld=True): each
+# cell's vertices re-solved from their planes in long double; the oracle's
+# double volume, interpolated by the primal clip from box-scale vertices, is
+# off by up to ~1e-11 on cells far smaller than the box).  FP32 path:
+# neighbour sets bit-exact, volumes 1e-5 relative.
 VOL_RTOL = {"f64": 1e-12, "f32": 1e-5}
-VOL_FLOOR = {"f64": 1e-14, "f32": 0.0}
 
 
 def note(msg: str):
@@ -36,16 +37,74 @@ def compare_rows(gpu_rp, gpu_col, orc, rows=None):
     return bad
 
 
-def volume_errors(gpu_vol, orc_vol, prec: str, box_vol: float = 1.0, rows=None):
-    g = np.asarray(gpu_vol, dtype=np.float64)
-    o = np.asarray(orc_vol, dtype=np.float64)
-    if rows is not None:
-        g, o = g[rows], o[rows]
-    n = len(np.asarray(orc_vol))
-    tol = VOL_RTOL[prec] * np.abs(o) + VOL_FLOOR[prec] * box_vol / max(n, 1)
+class VolumeCheck(tuple):
+    """(viol, rel), and how many cells the oracle's double volume itself was
+    off its long-double volume by more than 1e-12 (``oracle_off``)."""
+
+    def __new__(cls, viol, rel, oracle_off=0):
+        t = super().__new__(cls, (viol, rel))
+        t.viol, t.rel, t.oracle_off = viol, rel, oracle_off
+        return t
+
+
+def volume_errors(gpu_vol, orc: dict, prec: str, rows=None):
+    """Violations of the volume bar and relative errors, against the oracle's
+    long-double volume (``orc["volume_ld"]``, required for FP64) or its
+    double volume.  ``rows`` selects cells (indices into both arrays)."""
+    if prec == "f64" and "volume_ld" not in orc:
+        raise ValueError("the FP64 volume bar needs oracle.tessellate(..., volume_ld=True)")
+    ref = orc.get("volume_ld", orc["volume"])
+    idx = slice(None) if rows is None else np.asarray(rows)
+    g = np.asarray(gpu_vol, dtype=np.float64)[idx]
+    o = np.asarray(ref, dtype=np.float64)[idx]
     err = np.abs(g - o)
     rel = err / np.maximum(np.abs(o), 1e-300)
-    return err > tol, rel
+    off = 0
+    if "volume_ld" in orc:
+        od = np.asarray(orc["volume"], dtype=np.float64)[idx]
+        off = int((np.abs(od - o) > VOL_RTOL["f64"] * np.abs(o)).sum())
+    return VolumeCheck(err > VOL_RTOL[prec] * np.abs(o), rel, off)
+
+
+def ld_volumes(P, cells, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    """Volumes of the given cells in long double (64-bit mantissa) from the
+    combinatorics the oracle reports, computed independently of its own
+    long-double volume: each vertex is re-solved from its three planes
+    (triple_vertices), each face is the vertices naming its plane, ordered by
+    angle about their mean, and the volume is the sum of the tetrahedra
+    (generator, face mean, v_i, v_i+1)."""
+    import oracle
+    P = np.asarray(P, dtype=np.float64)
+    cells = np.asarray(cells, dtype=np.int64)
+    o = oracle.tessellate(P, lo, hi, vertices=True, cells=cells)
+    out = np.zeros(len(cells), dtype=np.float64)
+    for t, i in enumerate(cells):
+        a, b = int(o["vrow_ptr"][i]), int(o["vrow_ptr"][i + 1])
+        vpl = o["vplanes"][a:b]
+        rel, _ = triple_vertices(P, np.full(b - a, i), vpl, lo, hi, relative_ld=True)
+        vol = np.longdouble(0)
+        for f in np.unique(vpl):
+            on = np.nonzero((vpl == f).any(axis=1))[0]
+            if len(on) < 3:
+                continue
+            V = rel[on]
+            m = V.mean(axis=0)
+            # order by angle about the face mean, in the face's own plane
+            nrm = np.cross((V[0] - m).astype(np.float64), (V[1] - m).astype(np.float64))
+            if np.linalg.norm(nrm) == 0:
+                nrm = np.cross((V[0] - m).astype(np.float64), (V[2] - m).astype(np.float64))
+            e1 = (V[0] - m).astype(np.float64)
+            e1 /= np.linalg.norm(e1)
+            e2 = np.cross(nrm / np.linalg.norm(nrm), e1)
+            d = (V - m).astype(np.float64)
+            order = np.argsort(np.arctan2(d @ e2, d @ e1))
+            V = V[order]
+            W = np.roll(V, -1, axis=0)
+            det = (m[0] * (V[:, 1] * W[:, 2] - V[:, 2] * W[:, 1]) - m[1] * (V[:, 0] * W[:, 2] - V[:, 2] * W[:, 0])
+                   + m[2] * (V[:, 0] * W[:, 1] - V[:, 1] * W[:, 0]))
+            vol += np.abs(det.sum()) / 6
+        out[t] = float(vol)
+    return out
 
 
 def vertex_map(vrow_ptr, vxyz, vplanes, i):
@@ -53,10 +112,12 @@ def vertex_map(vrow_ptr, vxyz, vplanes, i):
     return {tuple(sorted(int(x) for x in vplanes[k])): np.asarray(vxyz[k]) for k in range(a, b)}
 
 
-def triple_vertices(P, owner, vplanes, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+def triple_vertices(P, owner, vplanes, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), relative_ld=False):
     """Each vertex as the meeting point of its three planes, solved by
     Cramer's rule in long double (64-bit mantissa), and the conditioning
-    kappa = |n_a| |n_b| |n_c| / |det| of the three plane normals.
+    kappa = |n_a| |n_b| |n_c| / |det| of the three plane normals.  With
+    ``relative_ld`` the vertices are returned in long double, relative to
+    their owner's generator.
 
     Plane ids: q >= 0 is the bisector of the owner and point q (normal
     P[q] - P[i], offset |P[q] - P[i]|^2 / 2 relative to P[i]); -1..-6 are
@@ -94,6 +155,8 @@ def triple_vertices(P, owner, vplanes, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
             m[:, :, k] = r
             y[:, k] = det(m) / D
         kappa = np.sqrt((n.astype(np.float64) ** 2).sum(2)).prod(1) / np.abs(D.astype(np.float64))
+    if relative_ld:
+        return y, kappa
     return (y + pi).astype(np.float64), kappa
 
 

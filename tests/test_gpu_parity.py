@@ -1,8 +1,10 @@
 """GPU parity: HIP path (through the C ABI) against the FP64 oracle.
 
 Bars: neighbour sets bit-exact on generic input; volumes within 1e-12
-relative (FP64 path; floor 1e-14 of the mean cell volume) or 1e-5 relative
-(FP32 path); grid sort bit-exact against a stable argsort; k-NN lists exact
+relative (FP64 path; a cell beyond it is arbitrated by its volume recomputed
+in long double from the oracle's vertex plane triples, and the GPU must be
+within 1e-12 of that) or 1e-5 relative (FP32 path); FP32 vertices within
+1e-5 R; grid sort bit-exact against a stable argsort; k-NN lists exact
 in FP64; certified-cell counts at fixed k equal to the oracle's k_needed
 prediction.
 """
@@ -224,12 +226,14 @@ def test_tessellate_parity(name, kind, n, dt, kw):
     P = getattr(gen, kind)(n, seed=0, dtype=dt)
     res = vt.tessellate(torch.from_numpy(P).cuda(), **kw)
     torch.cuda.synchronize()
-    orc = oracle.tessellate(P.astype(np.float64))
+    orc = oracle.tessellate(P.astype(np.float64), volume_ld=True)
     prec = kw.get("precision", "f64")
     bad = compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
     assert not bad, f"{len(bad)} rows differ, e.g. {bad[:5]}"
-    viol, rel = volume_errors(res.volume.cpu().numpy(), orc["volume"], prec)
-    note(f"  {name}: max rel vol err {rel.max():.3e}  stats {res.stats}")
+    ve = volume_errors(res.volume.cpu().numpy(), orc, prec)
+    viol, rel = ve
+    note(f"  {name}: max rel vol err {rel.max():.3e} (oracle's double volume off on {ve.oracle_off}) "
+         f"stats {res.stats}")
     assert not viol.any(), f"{viol.sum()} volumes out of tolerance, max rel {rel.max():.3e}"
     assert abs(res.volume.sum().item() - 1.0) < (1e-12 if prec == "f64" else 1e-6)
 
@@ -241,9 +245,9 @@ def test_anisotropic_box_and_boundary_points():
     P[:4] = [lo, hi, (lo[0], hi[1], lo[2]), (0.1, 0.1, 2.5)]
     P[4] = (hi[0], 0.125, 2.5)  # on a face
     res = vt.tessellate(torch.from_numpy(P).cuda(), box=(lo, hi), k0=32)
-    orc = oracle.tessellate(P, lo, hi)
+    orc = oracle.tessellate(P, lo, hi, volume_ld=True)
     assert not compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
-    viol, _ = volume_errors(res.volume.cpu().numpy(), orc["volume"], "f64", box_vol=2 * 0.25 * 1.0)
+    viol, _ = volume_errors(res.volume.cpu().numpy(), orc, "f64")
     assert not viol.any()
 
 
@@ -254,7 +258,7 @@ def test_tiny_inputs(n):
     assert res.row_ptr.shape[0] == n + 1
     if n == 0:
         return
-    orc = oracle.tessellate(P)
+    orc = oracle.tessellate(P, volume_ld=True)
     assert not compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
     np.testing.assert_allclose(res.volume.cpu().numpy(), orc["volume"], rtol=1e-12)
     assert res.stats["fallback_cells"] == 0  # lists shorter than k hold every other point
@@ -275,7 +279,7 @@ def test_bcc_lattice_volumes():
     bc = np.stack(np.meshgrid(h, h, h, indexing="ij"), -1).reshape(-1, 3)
     P = np.concatenate([sc, bc])
     res = vt.tessellate(torch.from_numpy(P).cuda(), k0=32)
-    orc = oracle.tessellate(P)
+    orc = oracle.tessellate(P, volume_ld=True)
     np.testing.assert_allclose(res.volume.cpu().numpy(), orc["volume"], rtol=1e-12, atol=1e-17)
 
 
@@ -317,7 +321,7 @@ def test_status_counts_match_kneeded(kind, prec):
 def test_vertices_parity(prec):
     P = gen.cluster(20_000, seed=10, dtype=np.float32, n_clusters=64)
     res = vt.tessellate(torch.from_numpy(P).cuda(), k0=64, precision=prec, vertices=True)
-    orc = oracle.tessellate(P.astype(np.float64), vertices=True)
+    orc = oracle.tessellate(P.astype(np.float64), vertices=True, volume_ld=True)
     vrp = res.vrow_ptr.cpu().numpy()
     vx = res.vxyz.cpu().numpy()
     vp = res.vplanes.cpu().numpy()
@@ -349,19 +353,19 @@ def test_vertices_parity(prec):
         assert ratio.max() <= 64
     else:
         # a float vertex whose forward error bound exceeds 16 eps |v|_inf
-        # (eps = 1e-6, the FP32 form's tolerance) is re-solved in double, so
-        # none is worse than that bound
+        # (eps = 1e-6, the FP32 form's tolerance) is re-solved in double; the
+        # bar is the FP32 form's 1e-5 R
         rel = err / R[rows]
-        assert np.percentile(rel, 99) <= 1e-6 and rel.max() <= 16e-6 * (1 + 1e-3)
+        assert np.percentile(rel, 99) <= 1e-6 and rel.max() <= 1e-5
 
 
 def test_host_fallback_forced():
     P = gen.uniform(20_000, seed=11, dtype=np.float32)
     res = vt.tessellate(torch.from_numpy(P).cuda(), k0=32, force_fail_every=3)
     assert res.stats["fallback_cells"] >= len(P) // 3
-    orc = oracle.tessellate(P.astype(np.float64))
+    orc = oracle.tessellate(P.astype(np.float64), volume_ld=True)
     assert not compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
-    viol, _ = volume_errors(res.volume.cpu().numpy(), orc["volume"], "f64")
+    viol, _ = volume_errors(res.volume.cpu().numpy(), orc, "f64")
     assert not viol.any()
 
 
@@ -409,7 +413,7 @@ def test_clip_stream_phase(prec):
     r = vt.clip_cells(srt, lists, 8, precision=prec, stream=True, grid=grid, cell_start=cs)
     st = r["status"].cpu().numpy()
     pn = perm.cpu().numpy()
-    orc = oracle.tessellate(P.astype(np.float64))
+    orc = oracle.tessellate(P.astype(np.float64), volume_ld=True)
     deg = np.diff(orc["row_ptr"])[pn]  # faces of each cell, by sorted index
     cap = np.nonzero(st == 2)[0]
     note(f"  stream {prec}: statuses {np.bincount(st, minlength=4).tolist()}; faces of overflowing cells "
@@ -429,7 +433,9 @@ def test_clip_stream_phase(prec):
     assert np.all(st == 0)
     ok = np.nonzero(st == 0)[0]
     vol = r["volume"].cpu().numpy()
-    viol, rel = volume_errors(vol[ok], orc["volume"][pn[ok]], prec)
+    vol_orig = np.zeros(len(pn))
+    vol_orig[pn[ok]] = vol[ok]
+    viol, rel = volume_errors(vol_orig, orc, prec, rows=pn[ok])
     assert not viol.any(), rel.max()
     cnt = r["nbr_count"].cpu().numpy()
     nbr = r["nbr"].cpu().numpy()
@@ -447,7 +453,7 @@ _ORC_CACHE = {}
 def _oracle_full(name):
     if name not in _ORC_CACHE:
         P = gen.make(name, seed=0)
-        _ORC_CACHE[name] = (P, oracle.tessellate(P.astype(np.float64)))
+        _ORC_CACHE[name] = (P, oracle.tessellate(P.astype(np.float64), volume_ld=True))
     return _ORC_CACHE[name]
 
 
@@ -459,11 +465,13 @@ def test_uniform_1m_every_cell(prec):
     res = vt.tessellate(torch.from_numpy(P).cuda(), k0=32, max_gpu_retries=1, precision=prec)
     bad = compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
     assert not bad, bad[:5]
-    viol, rel = volume_errors(res.volume.cpu().numpy(), orc["volume"], prec)
+    ve = volume_errors(res.volume.cpu().numpy(), orc, prec)
+    viol, rel = ve
     note(f"  uniform 1M {prec}: passes {res.stats['passes']} streamed {res.stats['streamed_cells']} "
-         f"max rel vol err {rel.max():.2e}")
+         f"max rel vol err {rel.max():.2e} (oracle's double volume off on {ve.oracle_off})")
     assert not viol.any()
-    assert abs(res.volume.double().sum().item() - 1.0) <= (1e-10 if prec == "f64" else 1e-6)
+    # pairwise summation (numpy) of the volumes: the cells tile the box
+    assert abs(np.sum(res.volume.cpu().numpy()) - 1.0) <= (1e-12 if prec == "f64" else 1e-6)
 
 
 def test_cluster_4m_fp32_report():
@@ -482,8 +490,8 @@ def test_cluster_4m_fp32_report():
     rng = np.random.default_rng(7)
     cells = np.sort(rng.choice(len(P), 3000, replace=False))
     P64 = P.astype(np.float64)
-    orc = oracle.tessellate(P64, cells=cells)
-    viol, rel = volume_errors(res.volume.cpu().numpy(), orc["volume"], "f32", rows=cells)
+    orc = oracle.tessellate(P64, cells=cells, volume_ld=True)
+    viol, rel = volume_errors(res.volume.cpu().numpy(), orc, "f32", rows=cells)
     note(f"  volume rel err p50 {np.median(rel):.2e} p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
     assert not viol.any()
     # vertices of the same cells from the clip call (sorted indices), FP32 path
@@ -514,4 +522,4 @@ def test_cluster_4m_fp32_report():
     note(f"  vertex err / R p50 {np.median(err):.2e} p99 {np.percentile(err, 99):.2e} max {err.max():.2e} "
          f"({len(err)} vertices of {len(ok)} cells)")
     assert len(ok) >= 0.99 * len(cells)
-    assert np.percentile(err, 99) <= 1e-6 and err.max() <= 16e-6 * (1 + 1e-3)
+    assert np.percentile(err, 99) <= 1e-6 and err.max() <= 1e-5

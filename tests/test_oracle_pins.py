@@ -9,7 +9,9 @@ the 8 octant centres, with their centroids and face areas); invariants
 (volumes tile the box, first moments add up to the box's, pyramids over the
 faces of interior cells fill the cell, symmetric neighbour relation, Euler's
 formula, equidistant vertices, empty spheres, equal face areas seen from both
-sides); and the Poisson-Voronoi mean face count.
+sides); the Poisson-Voronoi mean face count; and the work counters of the
+k_needed pass (planes tested, vertex evaluations, vertices created, R^2
+updates) by closed forms and by a Qhull replay of the nearest-first clipping.
 """
 import json
 import os
@@ -39,9 +41,10 @@ def test_oracle_matches_brute_force(seed):
     else:
         P = rng.random((n, 3))
     lo, hi = ((0, 0, 0), (1, 1, 1)) if seed % 4 else ((-0.1, 0.0, -0.3), (1.2, 1.0, 1.05))
-    r = oracle.tessellate(P, lo, hi, vertices=True)
+    r = oracle.tessellate(P, lo, hi, vertices=True, volume_ld=True)
     vol, nbrs, verts, areas, cents = brute.brute_cells(P, lo, hi, geometry=True)
     np.testing.assert_allclose(r["volume"], vol, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r["volume_ld"], vol, rtol=0, atol=1e-13)
     assert _rows(r) == nbrs
     want_area = np.array([areas[i][j] for i in range(len(P)) for j in nbrs[i]])
     np.testing.assert_allclose(r["area"], want_area, rtol=0, atol=1e-12)
@@ -309,3 +312,89 @@ def test_oracle_vertices_meet_their_three_planes():
     ref3, _ = triple_vertices(P, owner, wrong)
     moved = np.abs(ref3 - o["vxyz"]).max(1) / R[owner]
     assert np.median(np.nan_to_num(moved, nan=np.inf)) > 1e-3  # singular triples count as moved
+
+
+def _work_by_halfspaces(P, i, kwork):
+    """Work of nearest-first clipping of cell i with a list of ``kwork``,
+    replayed with Qhull: C_0 is the box; before bisector m the cell stops if
+    d_m^2 > 4 R_{m-1}^2; else plane m is tested against every vertex of
+    C_{m-1} (|V(C_{m-1})| evaluations), and if it cuts, C_m is the Qhull
+    intersection of the box with the first m bisectors, the vertices created
+    are those of C_m that were not inside vertices of C_{m-1}, and R^2 is
+    updated over every vertex of C_m."""
+    from scipy.spatial import HalfspaceIntersection
+    d2 = np.sum((P - P[i]) ** 2, axis=1)
+    order = [j for j in np.lexsort((np.arange(len(P)), d2)) if j != i]
+    ns0, cs0, _ = brute.halfspaces(P, i, (0, 0, 0), (1, 1, 1), subset=[])
+    corners = np.array([[(cs0[1] if b & 1 else -cs0[0]), (cs0[3] if b & 2 else -cs0[2]),
+                         (cs0[5] if b & 4 else -cs0[4])] for b in range(8)])
+    V = corners
+    tested = evals = created = r2 = 0
+    for m in range(1, min(kwork, len(P) - 1) + 1):
+        q = order[m - 1]
+        if d2[q] > 4 * np.max(np.sum(V ** 2, axis=1)):
+            break
+        tested += 1
+        evals += len(V)
+        n = P[q] - P[i]
+        s = V @ n - 0.5 * (n @ n)
+        if not np.any(s > 0):
+            continue
+        ns, cs, _ = brute.halfspaces(P, i, (0, 0, 0), (1, 1, 1), subset=order[:m])
+        H = HalfspaceIntersection(np.hstack([ns, -cs[:, None]]), _inner(ns, cs, P[i]))
+        Vm = H.intersections
+        created += len(Vm) - int(np.sum(~(s > 0)))
+        r2 += len(Vm)
+        V = Vm
+    return tested, evals, created, r2
+
+
+def test_work_counters_closed_forms():
+    """Two points split by a plane parallel to two walls: one plane tested
+    against the 8 box corners, 4 edges cut, R^2 over the 8 vertices of the
+    slab.  A third point whose bisector misses the slab adds 8 evaluations
+    and nothing else."""
+    two = oracle.kneeded(np.array([[0.1, 0.5, 0.5], [0.3, 0.5, 0.5]]), kcap=8, kwork=8)
+    assert [int(two[k][0]) for k in ("tested", "evals", "created", "r2upd")] == [1, 8, 4, 8]
+    three = oracle.kneeded(np.array([[0.1, 0.5, 0.5], [0.3, 0.5, 0.5], [0.6, 0.5, 0.5]]), kcap=8, kwork=8)
+    assert [int(three[k][0]) for k in ("tested", "evals", "created", "r2upd")] == [2, 16, 4, 8]
+    # a list of one stops the count after the first plane
+    one = oracle.kneeded(np.array([[0.1, 0.5, 0.5], [0.3, 0.5, 0.5], [0.6, 0.5, 0.5]]), kcap=8, kwork=1)
+    assert [int(one[k][0]) for k in ("tested", "evals", "created", "r2upd")] == [1, 8, 4, 8]
+    # the plane x + y + z = 3/2 through the cube's centre: 4 corners beyond it,
+    # its hexagonal section adds 6 vertices, 10 remain
+    c = oracle.kneeded(np.array([[0.05, 0.05, 0.05], [0.95, 0.95, 0.95]]), kcap=8, kwork=8)
+    assert [int(c[k][0]) for k in ("tested", "evals", "created", "r2upd")] == [1, 8, 6, 10]
+
+
+@pytest.mark.parametrize("kind,seed", [("uniform", 7), ("cluster", 8)])
+def test_work_counters_against_halfspaces(kind, seed):
+    """Every counter of the oracle's k_needed pass equals a Qhull replay."""
+    P = getattr(gen, kind)(300, seed=seed, dtype=np.float64)
+    cells = np.arange(0, 300, 15)
+    for kwork in (8, 32):
+        k = oracle.kneeded(P, cells=cells, kcap=kwork, kwork=kwork)
+        got = list(zip(k["tested"].tolist(), k["evals"].tolist(), k["created"].tolist(), k["r2upd"].tolist()))
+        ref = [_work_by_halfspaces(P, int(i), kwork) for i in cells]
+        assert got == ref
+
+
+def test_volume_ld_against_independent_long_double():
+    """The oracle's long-double volume (vertices re-solved from their planes)
+    equals an independent numpy long-double evaluation of the same cells
+    (faces ordered by angle, fanned from their mean), tiles the box, and
+    agrees with the double volume wherever the cell is not far smaller than
+    the box; on cluster cores the double volume is the one that drifts."""
+    from helpers import ld_volumes
+    P = gen.cluster(6000, seed=31, dtype=np.float32, n_clusters=6).astype(np.float64)
+    r = oracle.tessellate(P, volume_ld=True)
+    v, vl = r["volume"], r["volume_ld"]
+    assert abs(np.sum(vl) - 1.0) <= 1e-13
+    drift = np.abs(v - vl) / vl
+    off = np.nonzero(drift > 1e-12)[0]
+    pick = np.unique(np.concatenate([off[:40], np.arange(0, len(P), 150)]))
+    ref = ld_volumes(P, pick)
+    assert np.max(np.abs(vl[pick] - ref) / ref) <= 1e-14
+    # where the double volume drifts the cells are tiny next to the box
+    big = vl > 1e-3 / len(P)
+    assert np.all(drift[big] <= 1e-12)
