@@ -26,20 +26,50 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic work per cell of the method on the workload (nearest-first
 # clipping until the security radius certifies), measured by the oracle on a
-# 20000-cell sample with `python -m oracle.work_figures <workload> 20000`.
-ALGO_FLOPS_PER_CELL = {"cluster-16m-f32": 32586.95}
-
-# HBM bytes moved by all k_clip launches of one learned-k step, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy (profiles/clip_traffic_cluster16m_f32.md).
-# Valid for the clip kernel as it was measured: re-measure after changing it.
-TRAFFIC_BYTES_PER_STEP = {"cluster-16m-f32": 4.9143e10}
+# 20000-cell sample with `python -m oracle.work_figures <workload> 20000`:
+# 7 flops per vertex-plane evaluation, 40 per created vertex, 5 per vertex
+# norm of an R^2 update (5288.5 evaluations, 71.3 vertices created and 266.5
+# R^2 vertex norms per cell on cluster-16m-f32).
+ALGO_FLOPS_PER_CELL = {"cluster-16m-f32": 41204.79}
+FLOP_WEIGHTS = "7 per vertex-plane evaluation + 40 per created vertex + 5 per R^2 vertex norm"
 
 PEAK = {"hbm_gbs": 8000.0, "fp32_tflops": 157.3, "fp64_tflops": 78.6}
-SORT_BYTES_PER_POINT = {np.float32: 12 + 16 + 4, np.float64: 24 + 32 + 4}  # read pts, write record + perm
+
+
+def sort_bytes_per_point(dtype, n: int, ncells: int) -> float:
+    """Grid sort: read the points, write the 4-field records and perm, write
+    cell_start."""
+    e = 4 if dtype == np.float32 else 8
+    return 3 * e + 4 * e + 4 + 4.0 * (ncells + 1) / max(n, 1)
 
 
 def knn_bytes_per_query(k: int) -> int:
     return 16 + 4 * k  # read the query's record, write k indices
+
+
+def clip_traffic(workload: str):
+    """HBM bytes per step of all k_clip launches from the committed counter
+    summary, only while it was taken on the clip kernel as it stands (the
+    summary records the SHA-256 of clip.hip); None otherwise."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", f"clip_traffic_{workload.replace('-', '')}.md")
+    src = os.path.join(ROOT, "paper_2412_04514_amd", "csrc", "clip.hip")
+    try:
+        text = open(prof).read()
+    except OSError:
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    vals = {}
+    for ln in text.splitlines():
+        if ":" in ln and ln.strip().startswith("- "):
+            k, v = ln.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("clip.hip sha256") != sha:
+        return None
+    try:
+        return float(vals["bytes per step"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -61,6 +91,8 @@ def main(argv=None) -> int:
                          "0: the learned pass streams its uncertified cells directly")
     ap.add_argument("--no-faces", action="store_true", help="skip the run with face areas and centroids")
     ap.add_argument("--profile-step", action="store_true", help="one headline step only (for rocprofv3)")
+    ap.add_argument("--kmodel-blob", default="",
+                    help="k-model blob file: loaded if it exists (no training), else written after training")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (calibrates rocprofv3 byte counters)")
     args = ap.parse_args(argv)
@@ -91,7 +123,15 @@ def main(argv=None) -> int:
     if args.mode in ("auto", "learned"):
         try:
             from paper_2412_04514_amd import kmodel as km
-            kmodel = km.load_default(args.workload, max_gpu_retries=args.retries)
+            if args.kmodel_blob and os.path.exists(args.kmodel_blob):
+                with open(args.kmodel_blob, "rb") as fh:
+                    kmodel = km.KModel.load(fh.read())
+                log(f"[bench] k-model loaded from {args.kmodel_blob} (tau {kmodel.tau})")
+            else:
+                kmodel = km.load_default(args.workload, max_gpu_retries=args.retries)
+                if args.kmodel_blob:
+                    with open(args.kmodel_blob, "wb") as fh:
+                        fh.write(kmodel.save())
         except Exception as e:  # no trained model shipped for this workload
             if args.mode == "learned":
                 raise
@@ -102,22 +142,27 @@ def main(argv=None) -> int:
         headline = dict(precision="f32", kmodel=kmodel, tau=kmodel.tau, max_gpu_retries=args.retries)
         label = "learned-k FP32"
 
+    # The Infinity Cache (256 MB) would otherwise keep part of the sorted
+    # records from one step to the next: every timed step is preceded by a
+    # 1 GiB streaming pass, outside the step's own interval.
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+
     def run(cfg, steps, warmup, tag):
         for i in range(warmup):
             vt.tessellate(pts, **cfg)
             log(f"[bench] {tag} warmup {i + 1}/{warmup}")
         torch.cuda.synchronize()
         stats, per = [], []
-        t = time.perf_counter()
         for i in range(steps):
+            flush.fill_(float(i))
+            torch.cuda.synchronize()
             t1 = time.perf_counter()
             r = vt.tessellate(pts, **cfg)
             torch.cuda.synchronize()
             per.append((time.perf_counter() - t1) * 1e3)
             stats.append(r.stats)
             del r
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t) * 1e3 / steps
+        ms = float(np.sum(per)) / steps
         log(f"[bench] {tag}: {ms:.2f} ms/step (median {np.median(per):.2f}, min {min(per):.2f})")
         stats[-1]["_ms_median"] = float(np.median(per))
         stats[-1]["_ms_min"] = float(min(per))
@@ -159,29 +204,38 @@ def main(argv=None) -> int:
                      clip_ms=float(np.mean([s["ms_clip"] for s in statsf])),
                      assemble_ms=float(np.mean([s["ms_assemble"] for s in statsf])))
 
-    # roofline of the dominant kernel (largest share of the step)
+    # Rooflines of the three stages, from their HIP-event times inside the
+    # library (on the stream the kernels run on); the dominant one (largest
+    # share of the step) is the line's `roofline`.
+    ncells = vt.grid_plan(n).ncells
+    sbpp = sort_bytes_per_point(P.dtype.type, n, ncells)
+    sort_gbs = sbpp * n / (ms_sort / 1e3) / 1e9
+    knn_q = sum(p["cells"] for p in st0["passes"])
+    knn_bytes = sum(p["cells"] * knn_bytes_per_query(p["k"]) for p in st0["passes"])
+    if kmodel is not None:  # the feature pass is a 16-NN over every cell
+        knn_q += n
+        knn_bytes += n * knn_bytes_per_query(16)
+    knn_gbs = knn_bytes / ((ms_knn + ms_feat) / 1e3) / 1e9
+    flops = ALGO_FLOPS_PER_CELL.get(args.workload)
+    clip_tf = flops * n / (ms_clip / 1e3) / 1e12 if flops else None
+    stages = {
+        "sort": dict(bound="hbm", achieved=sort_gbs, peak=PEAK["hbm_gbs"], unit="GB/s",
+                     frac=sort_gbs / PEAK["hbm_gbs"], ms=ms_sort,
+                     per_unit=f"{sbpp:.2f} bytes per point (points read, records and perm written, cell starts)"),
+        "knn": dict(bound="hbm", achieved=knn_gbs, peak=PEAK["hbm_gbs"], unit="GB/s",
+                    frac=knn_gbs / PEAK["hbm_gbs"], ms=ms_knn + ms_feat, queries=knn_q,
+                    per_unit="16 + 4k bytes per query (record read, k indices written)"),
+        "clip": dict(bound="alu", achieved=clip_tf, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
+                     frac=(clip_tf / PEAK["fp32_tflops"]) if clip_tf else None, ms=ms_clip,
+                     per_unit=f"{flops} algorithmic flops per cell ({FLOP_WEIGHTS}; oracle work count)"),
+    }
     work = {"sort": ms_sort, "knn": ms_knn + ms_feat, "clip": ms_clip}
     dom = max(work, key=work.get)
-    if dom == "clip":
-        flops = ALGO_FLOPS_PER_CELL.get(args.workload)
-        ach = flops * n / (ms_clip / 1e3) / 1e12 if flops else None
-        traffic = TRAFFIC_BYTES_PER_STEP.get(args.workload) if kmodel is not None else None
-        roof = dict(bound="alu", achieved=ach, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
-                    frac=(ach / PEAK["fp32_tflops"]) if ach else None, traffic=traffic,
-                    kernel="k_clip (all launches of a step)",
-                    per_unit=f"{flops} algorithmic flops per cell (oracle work count)")
-    elif dom == "knn":
-        nq = sum(p["cells"] for p in st0["passes"])
-        byt = sum(p["cells"] * knn_bytes_per_query(p["k"]) for p in st0["passes"])
-        ach = byt / (ms_knn / 1e3) / 1e9
-        roof = dict(bound="hbm", achieved=ach, peak=PEAK["hbm_gbs"], unit="GB/s", frac=ach / PEAK["hbm_gbs"],
-                    traffic=None, kernel="k_knn (all launches of a step)", per_unit="16 + 4k bytes per query",
-                    queries=nq)
-    else:
-        byt = SORT_BYTES_PER_POINT[P.dtype.type] * n
-        ach = byt / (ms_sort / 1e3) / 1e9
-        roof = dict(bound="hbm", achieved=ach, peak=PEAK["hbm_gbs"], unit="GB/s", frac=ach / PEAK["hbm_gbs"],
-                    traffic=None, kernel="grid sort", per_unit="32 bytes per point (f32)")
+    roof = dict(stages[dom])
+    roof.pop("ms", None)
+    roof["kernel"] = {"clip": "k_clip (all launches of a step)", "knn": "k_knn (all launches of a step)",
+                      "sort": "grid sort kernels"}[dom]
+    roof["traffic"] = clip_traffic(args.workload) if (dom == "clip" and kmodel is not None) else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -215,7 +269,8 @@ def main(argv=None) -> int:
         "with_faces": faces,
         "stage_ms": {"sort": ms_sort, "knn": ms_knn, "features": ms_feat, "mlp": ms_mlp, "clip": ms_clip,
                      "assemble": mean("ms_assemble"), "fallback": mean("ms_fallback")},
-        "sort_gbs": SORT_BYTES_PER_POINT[P.dtype.type] * n / (ms_sort / 1e3) / 1e9,
+        "stages": stages,
+        "mall_flush": "1 GiB streamed between timed steps (outside each step's interval)",
         "passes": st0["passes"],
         "streamed_cells": st0["streamed_cells"], "fallback_cells": st0["fallback_cells"],
         "capacity_cells": st0["capacity_cells"], "rechecks": st0["rechecks"],

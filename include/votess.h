@@ -187,10 +187,14 @@ typedef struct {
 } votess_clip_opts;
 
 /* Clips the box by the bisectors of each cell's k-list, nearest first, and
- * stops at the security radius: before bisector m the cell is certified when
+ * stops at the security radius (paper, Summary section; the radius lemma of
+ * Ray et al. 2018 that it cites): before bisector m the cell is certified when
  * d_m^2 > 4 R^2 (R = farthest vertex from the generator); after the whole
  * list it is certified when d_k^2 > 4 R^2, or when the list holds all n-1
- * other points.
+ * other points.  With opts->stream, k = 0 is allowed (knn may be NULL): the
+ * fused form, where every cell is clipped straight from the grid rings
+ * around its generator (the stream phase from ring 0) and no k-NN list is
+ * computed or stored.
  *   cells      [nc] sorted indices (NULL = all n points, nc = n)
  *   knn        [nc,k] from votess_knn for the same cells
  *   status     [rows] u8 out: VOTESS_CELL_*
@@ -219,7 +223,8 @@ VOTESS_API votess_status votess_clip_cells(votess_ctx* ctx, const void* sorted, 
 typedef struct votess_kmodel votess_kmodel;
 
 typedef struct {
-  int32_t k0;               /* first list size (default 32) */
+  int32_t k0;               /* first list size (default 32); 0: the fused form (no k-NN pass, every
+                               cell clipped from the grid rings; needs gpu_stream, no kmodel) */
   int32_t max_gpu_retries;  /* doublings of k on the GPU after the first pass, up to k = 256
                                (default 1; the learned first pass ends at k = 64) */
   double pts_per_cell;      /* grid density (default 2) */
@@ -273,9 +278,11 @@ typedef struct {
 
 VOTESS_API void votess_params_default(votess_params* p_h);
 
-/* One call: grid sort, k-NN, clip with the GPU retry ladder (k, 2k, ...),
- * then the host fallback (exact CPU cell, unbounded k) for cells still
- * uncertified, then CSR assembly.  `pts` [n,3] dtype device, input order.
+/* One call (paper, Features section: the library function that computes the
+ * tessellation and returns the natural neighbours as a jagged array): grid
+ * sort, k-NN, clip with the GPU retry ladder (k, 2k, ...), then the host
+ * fallback (exact CPU cell, unbounded k) for cells still uncertified, then
+ * CSR assembly.  `pts` [n,3] dtype device, input order.
  * Rows of the result are in original order (or sorted order with
  * index_space = 1), neighbours ascending; with want_faces, area[e] is the
  * area of the face the row's cell shares with col[e], and centroid the

@@ -276,10 +276,11 @@ votess_status votess_clip_cells(votess_ctx* ctx, const void* sorted, votess_dtyp
   VT_TRY(check_box(box));
   if (!cells) nc = n;
   if (n < 0 || nc < 0 || n >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "clip: bad sizes");
-  if (k < 1 || k > 64) return fail(VOTESS_EINVAL, "clip: k must be in [1, 64]");
+  if (k < 0 || k > 64 || (k == 0 && !opts->stream))
+    return fail(VOTESS_EINVAL, "clip: k must be in [1, 64], or 0 with the stream phase");
   if (opts->max_nbr < 1) return fail(VOTESS_EINVAL, "clip: max_nbr must be >= 1");
   if (opts->max_vert > 0 && (!vcount || !verts || !vplanes)) return fail(VOTESS_EINVAL, "clip: null vertex buffers");
-  if (nc > 0 && (!sorted || !knn || !status || !nbr_count || !nbr || !volume))
+  if (nc > 0 && (!sorted || (k > 0 && !knn) || !status || !nbr_count || !nbr || !volume))
     return fail(VOTESS_EINVAL, "clip: null buffer");
   if (opts->precision == VOTESS_CLIP_F32_RECHECK && dtype != VOTESS_F32)
     return fail(VOTESS_EINVAL, "clip: F32_RECHECK needs F32 positions");
@@ -398,7 +399,10 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   votess_params P;
   votess_params_default(&P);
   if (params_in) P = *params_in;
-  if (!valid_k(P.k0)) return fail(VOTESS_EINVAL, "tessellate: k0=%d not in {8,12,16,24,32,48,64}", P.k0);
+  const bool fused = P.k0 == 0 && !P.kmodel;
+  if (P.k0 == 0 && (P.kmodel || !P.gpu_stream || P.force_fail_every))
+    return fail(VOTESS_EINVAL, "tessellate: k0=0 (no list) needs the stream phase and no k-model");
+  if (!fused && !valid_k(P.k0)) return fail(VOTESS_EINVAL, "tessellate: k0=%d not in {8,12,16,24,32,48,64}", P.k0);
   if (P.precision == VOTESS_CLIP_F32_RECHECK && dtype != VOTESS_F32)
     return fail(VOTESS_EINVAL, "tessellate: F32_RECHECK needs F32 positions");
   if (P.max_gpu_retries < 0 || P.max_gpu_retries > VOTESS_MAX_PASSES - 2)
@@ -493,7 +497,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   // largest bucket), up to the largest k-NN kernel
   const int k_first = P.kmodel ? 64 : P.k0;
   int nretry = 0;
-  for (int kk = k_first; nretry < P.max_gpu_retries && kk < kMaxK; ++nretry) kk = std::min(2 * kk, kMaxK);
+  for (int kk = k_first; !fused && nretry < P.max_gpu_retries && kk < kMaxK; ++nretry) kk = std::min(2 * kk, kMaxK);
 
   // cells that entered the stream phase so far (device counter 5)
   auto stream_entries = [&](int64_t& out_v) -> votess_status {
@@ -515,8 +519,8 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
                                 stream_last && nretry == 0, cur, S, st));
       k = 64;  // retries of the learned pass continue from the largest bucket
     } else {
-      VT_TRY(alloc_buf(ctx, knn, nn * (size_t)k * 4));
-      {
+      if (!fused) {
+        VT_TRY(alloc_buf(ctx, knn, nn * (size_t)k * 4));
         Timer T(st, &S.ms_knn);
         VT_TRY(launch_knn(ctx, sorted.p, dtype, n, GD, cell_start.get<int32_t>(), SG, nullptr, n, k, dist,
                           knn.get<int32_t>(), st));
@@ -526,7 +530,7 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
         ClipLaunch c = base;
         c.cells = nullptr;
         c.nc = n;
-        c.knn = knn.get<int32_t>();
+        c.knn = fused ? nullptr : knn.get<int32_t>();
         c.k = k;
         c.stream = stream_last && nretry == 0;
         VT_TRY(launch_clip(c, st));
@@ -564,8 +568,8 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     if (ncap == 0) return VOTESS_OK;
     S.capacity_cells += ncap;
     Buf knn2;
-    VT_TRY(alloc_buf(ctx, knn2, (size_t)ncap * kk * 4));
-    {
+    if (kk > 0) {  // (no list in the fused form: the large kernel streams from ring 0 too)
+      VT_TRY(alloc_buf(ctx, knn2, (size_t)ncap * kk * 4));
       Timer T(st, &S.ms_knn);
       VT_TRY(launch_knn(ctx, sorted.p, dtype, n, GD, cell_start.get<int32_t>(), SG, nxt, ncap, kk, dist,
                         knn2.get<int32_t>(), st));

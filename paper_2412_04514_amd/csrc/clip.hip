@@ -117,10 +117,38 @@ __device__ __forceinline__ double residual2(const V3<double>& n, double c, const
   return s + err;
 }
 
-// Vertex of three planes, refined once against its accurate residual: a
-// few ulps of |v| unless the normals are singular to within ~u.
-__device__ __forceinline__ V3<double> solve3_refined(const V3<double>& na, double ca, const V3<double>& nb,
-                                                     double cb, const V3<double>& nc, double cc) {
+// The same residual for a bisector plane (n, |n|^2 / 2) without rounding its
+// offset: c - n.v = sum_i n_i (n_i / 2 - v_i), each difference split by a
+// two-sum, each product by an FMA.  The double offset |n|^2 / 2 is rounded by
+// u c, which a vertex of nearly parallel planes amplifies by its
+// conditioning; this residual has no such term (n itself is exact for float
+// inputs).
+__device__ __forceinline__ double residual_bis(const V3<double>& n, const V3<double>& v) {
+#pragma clang fp contract(off)
+  double s = 0.0, err = 0.0;
+  const double a[3] = {n.x, n.y, n.z}, b[3] = {v.x, v.y, v.z};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double h = 0.5 * a[i];  // exact
+    const double d = h - b[i];    // h - b = d + ed exactly
+    const double z0 = d - h;
+    const double ed = (h - (d - z0)) + (-b[i] - z0);
+    const double p = a[i] * d;
+    const double ep = fma(a[i], d, -p);  // a d = p + ep exactly
+    const double t = s + p;              // s + p = t + es exactly
+    const double z = t - s;
+    const double es = (s - (t - z)) + (p - z);
+    s = t;
+    err += es + ep + a[i] * ed;
+  }
+  return s + err;
+}
+
+// Vertex of three planes, refined once against its accurate residual (for
+// the planes flagged as bisectors, with their offsets taken exactly): a few
+// ulps of |v| unless the normals are singular to within ~u.
+__device__ __forceinline__ V3<double> solve3_refined(const V3<double>& na, double ca, bool ba, const V3<double>& nb,
+                                                     double cb, bool bb, const V3<double>& nc, double cc, bool bc_) {
   const V3<double> bc = cross(nb, nc), ca_ = cross(nc, na), ab = cross(na, nb);
   const double inv = 1.0 / dot(na, bc);
   auto apply = [&](double x, double y, double z) -> V3<double> {
@@ -128,7 +156,8 @@ __device__ __forceinline__ V3<double> solve3_refined(const V3<double>& na, doubl
             (x * bc.z + y * ca_.z + z * ab.z) * inv};
   };
   const V3<double> v = apply(ca, cb, cc);
-  const V3<double> d = apply(residual2(na, ca, v), residual2(nb, cb, v), residual2(nc, cc, v));
+  const V3<double> d = apply(ba ? residual_bis(na, v) : residual2(na, ca, v), bb ? residual_bis(nb, v) : residual2(nb, cb, v),
+                             bc_ ? residual_bis(nc, v) : residual2(nc, cc, v));
   return {v.x + d.x, v.y + d.y, v.z + d.z};
 }
 
@@ -672,9 +701,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   // Points already in the list are skipped by their (d^2, sorted index) key,
   // points beyond the security radius by d^2 > 4 R^2.  The cell is final once
   // the scanned block of rings contains the flower box.
+  // With no list at all (k = 0) every cell starts here, at ring 0: the
+  // fused form, with no k-NN pass and no list in memory.
   if constexpr (STREAM) {
-    const int ik0 = (have && st == VOTESS_CELL_RADIUS) ? a.knn[(size_t)t_idx * a.k + a.k - 1] : -1;
-    const bool strm = ik0 >= 0;  // a full list that did not certify
+    const bool nolist = a.k == 0;
+    const int ik0 = (have && st == VOTESS_CELL_RADIUS && !nolist) ? a.knn[(size_t)t_idx * a.k + a.k - 1] : -1;
+    const bool strm = have && st == VOTESS_CELL_RADIUS && (nolist || ik0 >= 0);  // a full list that did not certify
     if (strm) st = ST_RUN;
     if (strm && j == 0 && a.counters) atomicAdd(&a.counters[5], 1ull);
     const GridDev& Gd = a.grid;
@@ -682,9 +714,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     const int cy = axis_cell(p64y, Gd.lo1, Gd.ih1, Gd.g1);
     const int cz = axis_cell(p64z, Gd.lo2, Gd.ih2, Gd.g2);
     const double gmarg = 1e-9 * fmax(Gd.hi0 - Gd.lo0, fmax(Gd.hi1 - Gd.lo1, Gd.hi2 - Gd.lo2));
-    R dk2 = R(0);
+    R dk2 = R(-1);  // no list: every candidate lies beyond it
     int ik = -1;
-    if (strm) {
+    if (strm && !nolist) {
       ik = ik0;
       const Rec4 q = rec[ik];
       dk2 = dist2_nc((R)q.x - px, (R)q.y - py, (R)q.z - pz);
@@ -1076,20 +1108,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   // planes with the vertex solved and refined in double
   auto corner_geom = [&](unsigned u, int t, bool exact, V3<double>& na, double& ca, V3<double>& nb_, double& cb,
                          V3<double>& nc, double& cc, V3<double>& v, bool refined = false) {
+    const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
     if (exact) {
-      plane64(u & 0xFF, na, ca);
-      plane64((u >> 8) & 0xFF, nb_, cb);
-      plane64((u >> 16) & 0xFF, nc, cc);
-      v = refined ? solve3_refined(na, ca, nb_, cb, nc, cc) : solve3<double>(na, ca, nb_, cb, nc, cc);
+      plane64(A, na, ca);
+      plane64(B, nb_, cb);
+      plane64(C, nc, cc);
+      v = refined ? solve3_refined(na, ca, pid[pb + A] >= 0, nb_, cb, pid[pb + B] >= 0, nc, cc, pid[pb + C] >= 0)
+                  : solve3<double>(na, ca, nb_, cb, nc, cc);
     } else if (refined) {
-      const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
       na = {(double)pnx[pb + A], (double)pny[pb + A], (double)pnz[pb + A]};
       ca = (double)pnc[pb + A];
       nb_ = {(double)pnx[pb + B], (double)pny[pb + B], (double)pnz[pb + B]};
       cb = (double)pnc[pb + B];
       nc = {(double)pnx[pb + C], (double)pny[pb + C], (double)pnz[pb + C]};
       cc = (double)pnc[pb + C];
-      v = solve3_refined(na, ca, nb_, cb, nc, cc);
+      // bisector offsets are taken exactly only where the cached plane holds
+      // the exact normal (double planes)
+      constexpr bool kExactN = sizeof(R) == 8;
+      v = solve3_refined(na, ca, kExactN && pid[pb + A] >= 0, nb_, cb, kExactN && pid[pb + B] >= 0, nc, cc,
+                         kExactN && pid[pb + C] >= 0);
     } else {
       const int A = u & 0xFF, B = (u >> 8) & 0xFF, C = (u >> 16) & 0xFF;
       na = {(double)pnx[pb + A], (double)pny[pb + A], (double)pnz[pb + A]};
@@ -1109,7 +1146,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
         if (u == kEmpty) continue;
         V3<double> na, nb_, nc, v;
         double ca, cb, cc;
-        corner_geom(u, t, exact, na, ca, nb_, cb, nc, cc, v);
+        // double planes: every vertex refined once (a vertex of nearly
+        // parallel planes is otherwise off by its conditioning times u R)
+        corner_geom(u, t, exact, na, ca, nb_, cb, nc, cc, v, exact || sizeof(R) == 8);
         const V3<double> eab = anchor(na, ca, nb_, cb), ebc = anchor(nb_, cb, nc, cc), eca = anchor(nc, cc, na, ca);
         const double fa = ca / dot(na, na), fb = cb / dot(nb_, nb_), fc = cc / dot(nc, nc);
         const V3<double> Fa = {fa * na.x, fa * na.y, fa * na.z};

@@ -26,6 +26,7 @@ GridDev to_dev(const votess_grid& g) {
 namespace {
 
 constexpr int kLdsSortMax = 4096; // larger cells sort their keys in global memory
+constexpr int kDenseBlocks = 1024; // blocks of the dense-cell pass (grid-stride over the dense cells)
 
 template <typename T>
 __global__ void k_cell_rank(const T* __restrict__ pts, int n, GridDev G, int* __restrict__ count,
@@ -330,6 +331,196 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(Tout* __restrict__ out,
   }
 }
 
+// Exclusive scan of a[0..cnt) in place by one 256-thread block (chunks of
+// 2048 with a running carry).
+__device__ void block_scan_inplace(int* a, int cnt) {
+  int carry = 0;
+  for (int base = 0; base < cnt; base += kScanTile) {
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int idx = base + (int)threadIdx.x * kScanItems + i;
+      v[i] = idx < cnt ? a[idx] : 0;
+      s += v[i];
+    }
+    int tot;
+    int run = block_excl_scan<int>(s, &tot) + carry;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int idx = base + (int)threadIdx.x * kScanItems + i;
+      if (idx < cnt) a[idx] = run;
+      run += v[i];
+    }
+    carry += tot;
+  }
+  __syncthreads();
+}
+
+// Counts of a dense cell's sub-cells live in LDS when there are at most this
+// many (the common case), else in the global scratch at the cell's range.
+constexpr int kCntLds = 4096;
+// A sub-cell holding more points than this (crowded: the points sit far
+// tighter than the central 90% box the sub-grid spans) has its cell ordered
+// by the bitonic network instead of the per-sub-cell rank count below.
+constexpr int kCrowd = 256;
+
+// One block per dense cell (grid-stride over the dense-cell list): plan the
+// cell's sub-grid (as k_order_big), then a counting sort by sub-cell -- LDS
+// atomic counts give each point its sub-cell and a provisional slot, a block
+// scan turns counts into the sub-cell starts (written to the record as they
+// are) -- and within a sub-cell each point's final rank is the number of its
+// points with a smaller original index.  Per-point scratch lives in global
+// memory at the cell's own range [b, b + len).
+template <typename T>
+__global__ __launch_bounds__(256) void k_order_dense(const typename Rec<T>::type* __restrict__ tmp,
+                                                     const int* __restrict__ cell_start, const int* __restrict__ big,
+                                                     const int* __restrict__ nbig, GridDev G,
+                                                     typename Rec<T>::type* __restrict__ out, int* __restrict__ perm,
+                                                     unsigned* __restrict__ g_sid, unsigned* __restrict__ g_rank,
+                                                     unsigned* __restrict__ g_slot, int* __restrict__ g_cnt,
+                                                     unsigned long long* __restrict__ gkey, unsigned* __restrict__ gval,
+                                                     int2* __restrict__ subinfo, int* __restrict__ sub_start,
+                                                     int* __restrict__ sub_total) {
+  __shared__ int s_cnt[kCntLds];
+  __shared__ double sbox[4][6];
+  __shared__ int shist[3][kSubBins];
+  __shared__ int soff, sm[3], s_crowd;
+  __shared__ double slo[3], sih[3];
+  const int nb = *nbig;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = blockIdx.x; q < nb; q += gridDim.x) {
+    const int c = big[q];
+    const int b = cell_start[c], len = cell_start[c + 1] - b;
+    // ---- sub-grid plan: bounding box, per-axis histograms, central 90%
+    double mn0 = 1e300, mn1 = 1e300, mn2 = 1e300, mx0 = -1e300, mx1 = -1e300, mx2 = -1e300;
+    for (int t = threadIdx.x; t < len; t += blockDim.x) {
+      const auto r = tmp[b + t];
+      mn0 = fmin(mn0, (double)r.x); mx0 = fmax(mx0, (double)r.x);
+      mn1 = fmin(mn1, (double)r.y); mx1 = fmax(mx1, (double)r.y);
+      mn2 = fmin(mn2, (double)r.z); mx2 = fmax(mx2, (double)r.z);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      mn0 = fmin(mn0, __shfl_xor(mn0, o, 64)); mx0 = fmax(mx0, __shfl_xor(mx0, o, 64));
+      mn1 = fmin(mn1, __shfl_xor(mn1, o, 64)); mx1 = fmax(mx1, __shfl_xor(mx1, o, 64));
+      mn2 = fmin(mn2, __shfl_xor(mn2, o, 64)); mx2 = fmax(mx2, __shfl_xor(mx2, o, 64));
+    }
+    if (lane == 0) {
+      sbox[wid][0] = mn0; sbox[wid][1] = mn1; sbox[wid][2] = mn2;
+      sbox[wid][3] = mx0; sbox[wid][4] = mx1; sbox[wid][5] = mx2;
+    }
+    for (int t = threadIdx.x; t < 3 * kSubBins; t += blockDim.x) (&shist[0][0])[t] = 0;
+    if (threadIdx.x == 0) s_crowd = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int nw = (int)(blockDim.x + 63) >> 6;
+      for (int w = 1; w < nw; ++w) {
+        mn0 = fmin(mn0, sbox[w][0]); mn1 = fmin(mn1, sbox[w][1]); mn2 = fmin(mn2, sbox[w][2]);
+        mx0 = fmax(mx0, sbox[w][3]); mx1 = fmax(mx1, sbox[w][4]); mx2 = fmax(mx2, sbox[w][5]);
+      }
+      sbox[0][0] = mn0; sbox[0][1] = mn1; sbox[0][2] = mn2;
+      sbox[0][3] = mx0; sbox[0][4] = mx1; sbox[0][5] = mx2;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < len; t += blockDim.x) {
+      const auto r = tmp[b + t];
+      const double x[3] = {(double)r.x, (double)r.y, (double)r.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double lo = sbox[0][a], w = sbox[0][3 + a] - lo;
+        const int bin = w > 0.0 ? (int)fmin((x[a] - lo) / w * kSubBins, (double)(kSubBins - 1)) : 0;
+        atomicAdd(&shist[a][bin], 1);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const int a = threadIdx.x;
+      const double lo = sbox[0][a], w = sbox[0][3 + a] - lo;
+      const int cut_lo = len / 20, cut_hi = len - len / 20;
+      int acc = 0, blo = 0, bhi = kSubBins - 1;
+      bool got_lo = false;
+      for (int i = 0; i < kSubBins; ++i) {
+        const int next = acc + shist[a][i];
+        if (!got_lo && next > cut_lo) { blo = i; got_lo = true; }
+        if (next >= cut_hi) { bhi = i; break; }
+        acc = next;
+      }
+      slo[a] = lo + w * ((double)blo / kSubBins);
+      sih[a] = fmax(w * ((double)(bhi + 1 - blo) / kSubBins), (a == 0 ? G.h0 : a == 1 ? G.h1 : G.h2) * 0x1p-30);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double e0 = sih[0], e1 = sih[1], e2 = sih[2];  // extents here
+      int m0, m1, m2;
+      plan_sub(len, e0, e1, e2, m0, m1, m2);
+      sm[0] = m0; sm[1] = m1; sm[2] = m2;
+      sih[0] = m0 / e0; sih[1] = m1 / e1; sih[2] = m2 / e2;
+      const int words = (kSubHead + m0 * m1 * m2 + 1 + 3) & ~3;
+      soff = atomicAdd(sub_total, words);
+    }
+    __syncthreads();
+    const int m0 = sm[0], m1 = sm[1], m2 = sm[2];
+    const int ns = m0 * m1 * m2;
+    const double lo0 = slo[0], lo1 = slo[1], lo2 = slo[2], ih0 = sih[0], ih1 = sih[1], ih2 = sih[2];
+    // ---- counting sort by sub-cell
+    int* cnt = ns + 1 <= kCntLds ? s_cnt : g_cnt + b;  // ns + 1 <= len / 2 + 1 <= len entries
+    for (int sc = threadIdx.x; sc <= ns; sc += blockDim.x) cnt[sc] = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < len; t += blockDim.x) {
+      const auto r = tmp[b + t];
+      const unsigned sid =
+          (unsigned)(sub_axis(r.x, lo0, ih0, m0) + m0 * (sub_axis(r.y, lo1, ih1, m1) + m1 * sub_axis(r.z, lo2, ih2, m2)));
+      g_sid[b + t] = sid;
+      g_rank[b + t] = (unsigned)atomicAdd(&cnt[sid], 1);
+    }
+    __syncthreads();
+    int crowd = 0;
+    for (int sc = threadIdx.x; sc < ns; sc += blockDim.x) crowd |= cnt[sc] > kCrowd;
+    if (crowd) s_crowd = 1;
+    block_scan_inplace(cnt, ns + 1);  // cnt[sc] = first point of sub-cell sc, cnt[ns] = len
+    int* rec = sub_start + soff;
+    if (threadIdx.x == 0) {
+      *(int4*)rec = make_int4(m0, m1, m2, 0);
+      *(double2*)(rec + 4) = make_double2(lo0, lo1);
+      *(double2*)(rec + 8) = make_double2(lo2, ih0);
+      *(double2*)(rec + 12) = make_double2(ih1, ih2);
+      subinfo[c] = make_int2(soff, ns);
+    }
+    for (int sc = threadIdx.x; sc <= ns; sc += blockDim.x) rec[kSubHead + sc] = cnt[sc];
+    if (!s_crowd) {
+      // provisional slots, then each point's rank among its sub-cell's ids
+      for (int t = threadIdx.x; t < len; t += blockDim.x)
+        g_slot[b + cnt[g_sid[b + t]] + (int)g_rank[b + t]] = (unsigned)Rec<T>::id(tmp[b + t]);
+      __syncthreads();
+      for (int t = threadIdx.x; t < len; t += blockDim.x) {
+        const auto r = tmp[b + t];
+        const unsigned id = (unsigned)Rec<T>::id(r);
+        const unsigned sid = g_sid[b + t];
+        const int s0 = cnt[sid], s1 = cnt[sid + 1];
+        int rank = 0;
+        for (int u = s0; u < s1; ++u) rank += g_slot[b + u] < id;
+        out[b + s0 + rank] = r;
+        perm[b + s0 + rank] = (int)id;
+      }
+    } else {
+      // crowded sub-cells: sort (sub-cell, original index) keys instead
+      unsigned long long* key = gkey + b;
+      unsigned* val = gval + b;
+      for (int t = threadIdx.x; t < len; t += blockDim.x) {
+        key[t] = ((unsigned long long)g_sid[b + t] << 32) | (unsigned)Rec<T>::id(tmp[b + t]);
+        val[t] = (unsigned)t;
+      }
+      __syncthreads();
+      block_bitonic(key, val, len);
+      for (int t = threadIdx.x; t < len; t += blockDim.x) {
+        out[b + t] = tmp[b + (int)val[t]];
+        perm[b + t] = (int)(unsigned)(key[t] & 0xffffffffu);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename Tin, typename Tout>
 votess_status scan_impl(const Tin* in, int64_t n, Tout* out, Workspace& ws, hipStream_t st) {
   const int64_t n_out = n + 1;
@@ -372,10 +563,11 @@ votess_status scan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, Worksp
 
 size_t grid_sort_workspace(int64_t n, int64_t ncells) {
   // cell/rank pairs, counts, unordered records (<= 32 B), dense-cell list,
-  // global sort keys and payloads, scan scratch
+  // global sort keys and payloads, the dense-cell scratch (sub-cell id,
+  // provisional slot, slot ids, counts: four ints per point), scan scratch
   return Workspace::align(n * 8) + Workspace::align(ncells * 4 + 4) + Workspace::align(n * 32) +
          Workspace::align(ncells * 4 + 64) + Workspace::align(n * 8) + Workspace::align(n * 4) +
-         scan_workspace(ncells) + 4096;
+         4 * Workspace::align(n * 4 + 4) + scan_workspace(ncells) + 4096;
 }
 
 // dense cells hold > 16 points each: sum of (16 + count / 2 + 1 + 3) <= n / 2 + 20 n / 17
@@ -392,6 +584,10 @@ votess_status launch_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dt
   int* nbig = ctx->d_counter;
   unsigned long long* gkey = ws.take<unsigned long long>(n > 0 ? n : 1);
   unsigned* gval = ws.take<unsigned>(n > 0 ? n : 1);
+  unsigned* g_sid = ws.take<unsigned>(n + 1);
+  unsigned* g_rank = ws.take<unsigned>(n + 1);
+  unsigned* g_slot = ws.take<unsigned>(n + 1);
+  int* g_cnt = ws.take<int>(n + 1);
   int* sub_total = ctx->d_counter + 1;
   VT_HIP(hipMemsetAsync(count, 0, (ncells + 1) * sizeof(int), st));
   VT_HIP(hipMemsetAsync(nbig, 0, 2 * sizeof(int), st));
@@ -411,14 +607,24 @@ votess_status launch_grid_sort(votess_ctx* ctx, const void* pts, votess_dtype dt
       k_scatter<float><<<nblk, TB, 0, st>>>((const float*)pts, n, cr, cell_start, (float4*)tmp);
       k_order_small<float><<<cblk, TB, 0, st>>>((const float4*)tmp, cell_start, (int)ncells, (float4*)sorted, perm,
                                                 big, nbig, (int2*)subinfo);
-      k_order_big<float><<<512, 256, 0, st>>>((const float4*)tmp, cell_start, big, nbig, G, (float4*)sorted, perm,
-                                              gkey, gval, (int2*)subinfo, sub_start, sub_total);
+      if (subinfo)
+        k_order_dense<float><<<kDenseBlocks, 256, 0, st>>>((const float4*)tmp, cell_start, big, nbig, G,
+                                                           (float4*)sorted, perm, g_sid, g_rank, g_slot, g_cnt, gkey,
+                                                           gval, (int2*)subinfo, sub_start, sub_total);
+      else
+        k_order_big<float><<<512, 256, 0, st>>>((const float4*)tmp, cell_start, big, nbig, G, (float4*)sorted, perm,
+                                                gkey, gval, (int2*)subinfo, sub_start, sub_total);
     } else {
       k_scatter<double><<<nblk, TB, 0, st>>>((const double*)pts, n, cr, cell_start, (double4*)tmp);
       k_order_small<double><<<cblk, TB, 0, st>>>((const double4*)tmp, cell_start, (int)ncells, (double4*)sorted,
                                                  perm, big, nbig, (int2*)subinfo);
-      k_order_big<double><<<512, 256, 0, st>>>((const double4*)tmp, cell_start, big, nbig, G, (double4*)sorted, perm,
-                                               gkey, gval, (int2*)subinfo, sub_start, sub_total);
+      if (subinfo)
+        k_order_dense<double><<<kDenseBlocks, 256, 0, st>>>((const double4*)tmp, cell_start, big, nbig, G,
+                                                            (double4*)sorted, perm, g_sid, g_rank, g_slot, g_cnt,
+                                                            gkey, gval, (int2*)subinfo, sub_start, sub_total);
+      else
+        k_order_big<double><<<512, 256, 0, st>>>((const double4*)tmp, cell_start, big, nbig, G, (double4*)sorted,
+                                                 perm, gkey, gval, (int2*)subinfo, sub_start, sub_total);
     }
     VT_HIP(hipGetLastError());
   }

@@ -72,11 +72,31 @@ def _sub_records(P, grid, cid, sub_start, subinfo):
 
 # ------------------------------------------------------------------ grid sort
 
+def _one_giant_cell(n, crowded, seed=0):
+    """n/3 uniform points plus 2n/3 in a Gaussian (sigma 1e-4) inside one grid
+    cell, so that the cell holds far more than 8192 points (its
+    sub-cell counts no longer fit in LDS); ``crowded`` puts n/8 of those in a
+    far tighter core (sigma 3e-7), so that single sub-cells hold hundreds of
+    points.  Exact duplicates are dropped."""
+    rng = np.random.default_rng(seed)
+    c = 0.3  # well inside one grid cell for the grid sizes n gives (32 to 34 per axis)
+    parts = [rng.random((n // 3, 3)), c + 1e-4 * rng.standard_normal((2 * n // 3 - (n // 8 if crowded else 0), 3))]
+    if crowded:
+        parts.append(c + 3e-7 * rng.standard_normal((n // 8, 3)))
+    P = np.concatenate(parts).astype(np.float32)
+    P = np.unique(P[np.all((P >= 0) & (P < 1), axis=1)], axis=0)
+    return P[rng.permutation(len(P))]
+
+
 @pytest.mark.parametrize("kind,n,dt", [("uniform", 1 << 20, np.float32), ("cluster", 1 << 20, np.float32),
-                                       ("uniform", 10_000, np.float64), ("cluster", 3000, np.float64)])
+                                       ("uniform", 10_000, np.float64), ("cluster", 3000, np.float64),
+                                       ("giant", 70_000, np.float32), ("crowded", 70_000, np.float32)])
 def test_grid_sort_bit_exact(kind, n, dt):
     note(f"grid_sort {kind} n={n} {dt.__name__}")
-    P = getattr(gen, kind)(n, seed=0, dtype=dt)
+    if kind in ("giant", "crowded"):
+        P = _one_giant_cell(n, kind == "crowded")
+    else:
+        P = getattr(gen, kind)(n, seed=0, dtype=dt)
     pts = torch.from_numpy(P).cuda()
     cs, perm, srt, grid = vt.grid_sort(pts)
     cid = _cells_np(P, grid)
@@ -92,7 +112,8 @@ def test_grid_sort_bit_exact(kind, n, dt):
     assert np.array_equal(ib, ref_perm)
     # sub-cell starts of (a sample of) the dense cells
     dense = sorted(recs)
-    note(f"  {len(dense)} dense cells, sub-cells per dense cell up to {max([r[1] for r in recs.values()] or [0])}")
+    note(f"  {len(dense)} dense cells, sub-cells per dense cell up to {max([r[1] for r in recs.values()] or [0])}, "
+         f"points per cell up to {np.diff(ref_cs).max()}")
     for c in dense[:: max(1, len(dense) // 200)]:
         off, ns = recs[c]
         a, b = ref_cs[c], ref_cs[c + 1]
@@ -523,3 +544,23 @@ def test_cluster_4m_fp32_report():
          f"({len(err)} vertices of {len(ok)} cells)")
     assert len(ok) >= 0.99 * len(cells)
     assert np.percentile(err, 99) <= 1e-6 and err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("kind,n,prec", [("uniform", 20_000, "f64"), ("cluster", 100_000, "f32"),
+                                         ("cluster", 100_000, "f64"), ("uniform", 3, "f64"), ("uniform", 1, "f32")])
+def test_fused_no_list_every_cell(kind, n, prec):
+    """The fused form (k0 = 0): no k-NN pass, every cell clipped straight
+    from the grid rings around its generator; every neighbour set and volume
+    against the oracle."""
+    dt = np.float64 if (prec == "f64" and kind == "uniform") else np.float32
+    P = getattr(gen, kind)(n, seed=17, dtype=dt)
+    res = vt.tessellate(torch.from_numpy(P).cuda(), k0=0, precision=prec)
+    st = res.stats
+    assert st["ms_knn"] == 0.0 and st["passes"][0]["k"] == 0
+    orc = oracle.tessellate(P.astype(np.float64), volume_ld=True)
+    bad = compare_rows(res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), orc)
+    assert not bad, bad[:5]
+    ve = volume_errors(res.volume.cpu().numpy(), orc, prec)
+    note(f"  fused {kind} {n} {prec}: max rel vol err {ve.rel.max(initial=0):.2e}; stats {st['passes']} "
+         f"streamed {st['streamed_cells']} capacity {st['capacity_cells']} host {st['fallback_cells']}")
+    assert not ve.viol.any()
