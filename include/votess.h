@@ -241,6 +241,12 @@ typedef struct {
                                cells by grid rings (no bound on k) instead of leaving
                                them to the host */
   int32_t want_faces;       /* 1: also return face areas and cell centroids */
+  int32_t periodic;         /* 1: the box is a 3-torus (points in [lo, hi)): every cell is the region
+                               nearer its generator than any periodic image of any point; a row lists
+                               the index of each point whose image shares a face, once per image.
+                               Clipping is FP64 (a float point's periodic image is not a float in
+                               general).  Not with kmodel, want_vertices, index_space 1 or
+                               force_fail_every. */
 } votess_params;
 
 #define VOTESS_MAX_PASSES 8

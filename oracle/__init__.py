@@ -25,7 +25,8 @@ _SRC = os.path.join(_HERE, "voronoi_oracle.cpp")
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-ERRORS = {1: "bad box", 2: "point outside the box", 3: "duplicate point"}
+ERRORS = {1: "bad box", 2: "point outside the box", 3: "duplicate point",
+          4: "periodic boxes keep no vertices and clip with the certificate", 5: "image shift out of range"}
 
 
 def build(force: bool = True) -> str:
@@ -79,7 +80,7 @@ class OracleError(ValueError):
 
 
 def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False, vertices=False,
-               threads=0, cells=None, volume_ld=False) -> dict:
+               threads=0, cells=None, volume_ld=False, periodic=False) -> dict:
     """Exact cells of every point (rows in input order, neighbours ascending).
 
     With ``cells`` (indices), only those rows are computed; the other rows are
@@ -92,14 +93,19 @@ def tessellate(points, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), all_planes=False,
     ``vrow_ptr, vxyz [nv,3], vplanes [nv,3], vdeg``.  With ``volume_ld`` also
     ``volume_ld``: each cell's volume in long double from its vertices re-solved
     from their planes (free of the box-scale rounding the primal clip leaves
-    in small cells).
+    in small cells).  With ``periodic`` the box is a 3-torus: every cell is the
+    region nearer its generator than any image of any point, neighbours are
+    the indices of the points whose images share a face with it (an index
+    once per such image; a cell may neighbour images of its own generator
+    when there are few points), centroids are not wrapped into the box, and
+    points must lie in [lo, hi).
     """
     lib = _load()
     P = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
     n = P.shape[0]
     lo_, hi_ = _box(lo, hi)
     h = ctypes.c_void_p()
-    flags = (1 if all_planes else 0) | (2 if vertices else 0) | (4 if volume_ld else 0)
+    flags = (1 if all_planes else 0) | (2 if vertices else 0) | (4 if volume_ld else 0) | (8 if periodic else 0)
     c = None if cells is None else np.ascontiguousarray(cells, dtype=np.int64)
     rc = lib.orc_tessellate(_ptr(P), n, _ptr(lo_), _ptr(hi_), _ptr(c), 0 if c is None else c.shape[0], flags,
                             threads, ctypes.byref(h))

@@ -36,6 +36,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <tuple>
 #include <vector>
 #include <omp.h>
 
@@ -226,7 +227,8 @@ inline void planeL(int64_t id, const double* P, int64_t i, const double* lo, con
   }
 }
 
-double volume_ld(const Poly& C, const double* P, int64_t i, const double* lo, const double* hi) {
+template <typename PlaneFn>
+double volume_ld_with(const Poly& C, PlaneFn plane) {
   const size_t nv = C.v.size();
   std::vector<std::vector<int64_t>> inc(nv);
   for (size_t k = 0; k < C.f.size(); ++k)
@@ -240,9 +242,9 @@ double volume_ld(const Poly& C, const double* P, int64_t i, const double* lo, co
     if (s.size() < 3) continue;
     V3L na, nb, nc;
     LD ca, cb, cc;
-    planeL(s[0], P, i, lo, hi, na, ca);
-    planeL(s[1], P, i, lo, hi, nb, cb);
-    planeL(s[2], P, i, lo, hi, nc, cc);
+    plane(s[0], na, ca);
+    plane(s[1], nb, cb);
+    plane(s[2], nc, cc);
     const V3L bc = crossL(nb, nc), ca_ = crossL(nc, na), ab = crossL(na, nb);
     const LD det = dotL(na, bc);
     if (det == 0) continue;
@@ -253,6 +255,10 @@ double volume_ld(const Poly& C, const double* P, int64_t i, const double* lo, co
   for (const auto& cyc : C.f)
     for (size_t k = 1; k + 1 < cyc.size(); ++k) vol += dotL(w[cyc[0]], crossL(w[cyc[k]], w[cyc[k + 1]]));
   return (double)(vol / 6);
+}
+
+double volume_ld(const Poly& C, const double* P, int64_t i, const double* lo, const double* hi) {
+  return volume_ld_with(C, [&](int64_t id, V3L& n, LD& c) { planeL(id, P, i, lo, hi, n, c); });
 }
 
 // ---------------------------------------------------------------------------
@@ -435,6 +441,112 @@ struct SortedStream {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Periodic boxes (the box is a 3-torus of periods L = hi - lo): the cell of
+// p_i is the set of points of R^3 nearer to p_i than to every image
+// p_j + m L (m in Z^3, (j, m) != (i, 0)).  It lies in the cube p_i +- L/2,
+// whose faces are exactly the bisectors with p_i's own six nearest images,
+// so that cube is the starting polytope; the other images are enumerated by
+// Chebyshev rings of the grid unrolled over R^3 (cell u maps to grid cell
+// u mod g with image shift floor(u / g)).  A plane is named by its point
+// and image shift: id = j * 32^3 + (mx + 15) + 32 (my + 15) + 32^2 (mz + 15),
+// shifts -15..16 per axis (the cell lies within |L| / 2 of p_i; a ring
+// enumeration over an elongated box with few grid cells may still need
+// several periods along its short axes).
+constexpr int64_t kShiftCodes = 32768;
+inline int64_t image_id(int64_t j, int mx, int my, int mz) {
+  return j * kShiftCodes + (mx + 15) + 32 * (my + 15) + 1024 * (mz + 15);
+}
+inline void image_of(int64_t id, int64_t& j, int m[3]) {
+  j = id / kShiftCodes;
+  int64_t c = id % kShiftCodes;
+  m[0] = (int)(c % 32) - 15;
+  m[1] = (int)((c / 32) % 32) - 15;
+  m[2] = (int)(c / 1024) - 15;
+}
+inline int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// returns false if an image shift falls outside -15..16
+bool exact_cell_periodic(const Grid& G, const double* P, const double* lo, const double* hi, int64_t i, Poly& C,
+                         Work& w) {
+  const V3 p = {P[3 * i], P[3 * i + 1], P[3 * i + 2]};
+  double L[3], clo[3], chi[3];
+  int c[3];
+  double ext = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    L[a] = hi[a] - lo[a];
+    clo[a] = p[a] - 0.5 * L[a];
+    chi[a] = p[a] + 0.5 * L[a];
+    c[a] = G.coord(p[a], a);
+    ext = std::max(ext, L[a]);
+  }
+  // the cube p +- L/2 built directly in seed-relative coordinates, so that
+  // its corners are exactly +-L/2 (the bisectors of farther images of p_i
+  // pass exactly through its edges and corners and must not cut them)
+  C.box(clo, chi, p);
+  for (int k = 0; k < 8; ++k)
+    C.v[k] = {(k & 1) ? 0.5 * L[0] : -0.5 * L[0], (k & 2) ? 0.5 * L[1] : -0.5 * L[1], (k & 4) ? 0.5 * L[2] : -0.5 * L[2]};
+  C.fid = {image_id(i, -1, 0, 0), image_id(i, 1, 0, 0), image_id(i, 0, -1, 0),
+           image_id(i, 0, 1, 0), image_id(i, 0, 0, -1), image_id(i, 0, 0, 1)};
+  const double margin = 1e-9 * ext;
+  std::vector<std::tuple<double, int64_t, V3>> ord;
+  for (int r = 0;; ++r) {
+    ord.clear();
+    for (int dz = -r; dz <= r; ++dz)
+      for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) {
+          if (std::max({std::abs(dx), std::abs(dy), std::abs(dz)}) != r) continue;
+          const int64_t u[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+          int m[3];
+          int64_t wc[3];
+          for (int a = 0; a < 3; ++a) {
+            m[a] = (int)floor_div(u[a], G.g[a]);
+            wc[a] = u[a] - (int64_t)m[a] * G.g[a];
+            if (m[a] < -15 || m[a] > 16) return false;
+          }
+          const int64_t cell = wc[0] + (int64_t)G.g[0] * (wc[1] + (int64_t)G.g[1] * wc[2]);
+          for (int64_t t = G.start[cell]; t < G.start[cell + 1]; ++t) {
+            const int64_t j = G.idx[t];
+            if (j == i && m[0] == 0 && m[1] == 0 && m[2] == 0) continue;
+            // (p_j - p_i) + m L: exact m L for p_i's own images
+            const V3 nrm = {(P[3 * j] - p[0]) + m[0] * L[0], (P[3 * j + 1] - p[1]) + m[1] * L[1],
+                            (P[3 * j + 2] - p[2]) + m[2] * L[2]};
+            ord.push_back({dot3(nrm, nrm), image_id(j, m[0], m[1], m[2]), nrm});
+          }
+        }
+    std::sort(ord.begin(), ord.end(), [](const auto& a, const auto& b) {
+      return std::get<0>(a) < std::get<0>(b) || (std::get<0>(a) == std::get<0>(b) && std::get<1>(a) < std::get<1>(b));
+    });
+    double r2 = C.radius2();
+    for (const auto& e : ord) {
+      if (std::get<0>(e) > 4.0 * r2) break;  // cannot cut; later ones are farther
+      if (C.clip(std::get<2>(e), 0.5 * std::get<0>(e), std::get<1>(e), w)) r2 = C.radius2();
+    }
+    // distance from p to the nearest face of the unrolled block of rings 0..r
+    double rho = std::numeric_limits<double>::infinity();
+    for (int a = 0; a < 3; ++a) {
+      const double h = L[a] / G.g[a];
+      rho = std::min(rho, p[a] - (lo[a] + (c[a] - r) * h));
+      rho = std::min(rho, (lo[a] + (c[a] + r + 1) * h) - p[a]);
+    }
+    rho -= margin;
+    if (rho > 0.0 && rho * rho > 4.0 * r2) break;
+  }
+  return true;
+}
+
+double volume_ld_periodic(const Poly& C, const double* P, int64_t i, const double* lo, const double* hi) {
+  return volume_ld_with(C, [&](int64_t id, V3L& n, LD& c) {
+    int64_t j;
+    int m[3];
+    image_of(id, j, m);
+    n = {(LD)P[3 * j] + (LD)m[0] * ((LD)hi[0] - (LD)lo[0]) - (LD)P[3 * i],
+         (LD)P[3 * j + 1] + (LD)m[1] * ((LD)hi[1] - (LD)lo[1]) - (LD)P[3 * i + 1],
+         (LD)P[3 * j + 2] + (LD)m[2] * ((LD)hi[2] - (LD)lo[2]) - (LD)P[3 * i + 2]};
+    c = dotL(n, n) / 2;
+  });
+}
+
 struct Result {
   int64_t n = 0;
   std::vector<int64_t> row_ptr;
@@ -459,13 +571,23 @@ typedef struct Result orc_result;
 
 // Computes every cell, or only the cells listed in `cells` (others are left
 // empty).  flags: 1 = clip by all other points (no certificate), 2 = keep
-// vertices, 4 = also the long-double volume of each cell.  Returns 0, or 1
-// bad box, 2 point outside box, 3 duplicate.
+// vertices, 4 = also the long-double volume of each cell, 8 = periodic box
+// (neighbours are the indices of the points whose images share a face, a
+// point appearing once per image; vertices are not kept; points must lie in
+// [lo, hi)).  Returns 0, or 1 bad box, 2 point outside box, 3 duplicate,
+// 4 unsupported flag combination, 5 image shift out of range.
 int orc_tessellate(const double* P, int64_t n, const double* lo, const double* hi, const int64_t* cells, int64_t nc,
                    int flags, int nthreads, orc_result** out) {
   *out = nullptr;
+  const bool periodic = flags & 8;
+  if (periodic && (flags & 3)) return 4;
   const int bad = validate(P, n, lo, hi);
   if (bad) return bad;
+  if (periodic)
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a)
+        if (!(P[3 * i + a] < hi[a])) return 2;
+  int shift_error = 0;
   Grid G;
   G.build(P, n, lo, hi);
   const bool all = flags & 1, keepv = flags & 2, want_ld = flags & 4;
@@ -488,9 +610,17 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
     if (i < 0 || i >= n) continue;
     Poly C;
     Work w;
-    exact_cell(G, P, n, lo, hi, i, all, C, w);
+    if (periodic) {
+      if (!exact_cell_periodic(G, P, lo, hi, i, C, w)) {
+#pragma omp atomic write
+        shift_error = 1;
+        continue;
+      }
+    } else {
+      exact_cell(G, P, n, lo, hi, i, all, C, w);
+    }
     res->vol[i] = C.volume();
-    if (want_ld) res->vol_ld[i] = volume_ld(C, P, i, lo, hi);
+    if (want_ld) res->vol_ld[i] = periodic ? volume_ld_periodic(C, P, i, lo, hi) : volume_ld(C, P, i, lo, hi);
     const V3 mom = C.moment();
     for (int a = 0; a < 3; ++a) res->cen[3 * i + a] = P[3 * i + a] + (res->vol[i] > 0.0 ? mom[a] / res->vol[i] : 0.0);
     res->work[4 * i + 0] = w.tested;
@@ -503,7 +633,7 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
       edges2 += (int64_t)C.f[k].size();
       if (C.fid[k] < 0) continue;
       const double a = C.face_area(k);
-      if (a > 0.0) row.push_back({(int32_t)C.fid[k], a});
+      if (a > 0.0) row.push_back({(int32_t)(periodic ? C.fid[k] / kShiftCodes : C.fid[k]), a});
     }
     res->euler[i] = (int32_t)((int64_t)C.v.size() - edges2 / 2 + (int64_t)C.f.size());
     std::sort(row.begin(), row.end());
@@ -524,6 +654,10 @@ int orc_tessellate(const double* P, int64_t n, const double* lo, const double* h
         vd[i].push_back((int32_t)s.size());
       }
     }
+  }
+  if (shift_error) {
+    delete res;
+    return 5;
   }
   res->row_ptr.assign(n + 1, 0);
   for (int64_t i = 0; i < n; ++i) res->row_ptr[i + 1] = res->row_ptr[i] + (int64_t)nb[i].size();

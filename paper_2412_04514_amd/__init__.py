@@ -253,11 +253,13 @@ def tessellate(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), k0: int = 32, m
                precision: str = "f64", eps: float = 1e-6, pts_per_cell: float = 2.0, kmodel=None, tau: float = 0.9,
                vertices: bool = False, index_space: str = "original", host_fallback: bool = True,
                host_threads: int = 0, force_fail_every: int = 0, gpu_stream: bool = True, faces: bool = False,
-               ctx: Context | None = None) -> Result:
+               periodic: bool = False, ctx: Context | None = None) -> Result:
     """Voronoi cells of ``points`` [n,3] (cuda, float32/float64) clipped to ``box``.
 
     With ``faces``, also the area of every neighbour's face (``area``, next to
-    ``col``) and the cell centroids (``centroid``)."""
+    ``col``) and the cell centroids (``centroid``).  With ``periodic`` the box
+    is a 3-torus (points in [lo, hi)): rows list the index of every point whose
+    image shares a face with the cell, once per image."""
     ctx = ctx or Context.get(points.device.index)
     pts = points.contiguous()
     p = _lib.Params()
@@ -276,6 +278,7 @@ def tessellate(points: torch.Tensor, box=((0, 0, 0), (1, 1, 1)), k0: int = 32, m
     p.force_fail_every = force_fail_every
     p.gpu_stream = int(bool(gpu_stream))
     p.want_faces = int(bool(faces))
+    p.periodic = int(bool(periodic))
     r = _lib.Result()
     b = _box(box)
     n = pts.shape[0]

@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("precision", C.c_int), ("eps", C.c_double), ("kmodel", C.c_void_p), ("tau", C.c_double),
                 ("want_vertices", C.c_int32), ("index_space", C.c_int32), ("host_fallback", C.c_int32),
                 ("host_threads", C.c_int32), ("force_fail_every", C.c_int32), ("gpu_stream", C.c_int32),
-                ("want_faces", C.c_int32)]
+                ("want_faces", C.c_int32), ("periodic", C.c_int32)]
 
 
 class Stats(C.Structure):

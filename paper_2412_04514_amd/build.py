@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libvotess.so")
 ARCH = os.environ.get("VOTESS_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["grid_sort.hip", "knn.hip", "clip.hip", "assemble.hip", "learned.hip", "api.cpp", "fallback.cpp"]
+SOURCES = ["grid_sort.hip", "knn.hip", "clip.hip", "assemble.hip", "learned.hip", "periodic.hip", "api.cpp",
+           "fallback.cpp"]
 HEADERS = ["internal.h", "device_common.h", os.path.join("..", "..", "include", "votess.h")]
 
 FLAGS = [

@@ -386,6 +386,57 @@ __global__ void k_force_fail(uint8_t* status, int n, int every) {
   if (s < n && s % every == 0) status[s] = VOTESS_CELL_RADIUS;
 }
 
+// Rows of host-fallback cells longer than the per-cell staging, written
+// straight into the result: neighbours (with their face areas) mapped to the
+// output index space and sorted ascending at row_ptr[r], or vertices (plane
+// ids mapped likewise) at vrow_ptr[r].  Copies on `st` from host staging that
+// lives until the final synchronisation.
+votess_status write_long_rows(const std::vector<int>& rows, const std::vector<HostCellOut>& cells,
+                              const std::vector<int32_t>& ids, const int32_t* perm_d, int n, int index_space,
+                              bool faces, const int64_t* row_ptr, int32_t* col, double* area, const int64_t* vrow_ptr,
+                              double* vxyz, int32_t* vplanes, hipStream_t st) {
+  if (rows.empty()) return VOTESS_OK;
+  std::vector<int32_t> perm_h;
+  if (index_space == 0) {
+    perm_h.resize(n);
+    VT_HIP(hipMemcpyAsync(perm_h.data(), perm_d, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+  }
+  std::vector<int64_t> off(rows.size(), 0);
+  const int64_t* rp = col ? row_ptr : vrow_ptr;
+  VT_HIP(hipStreamSynchronize(st));
+  auto map = [&](int32_t x) { return (x < 0 || index_space != 0) ? x : perm_h[x]; };
+  for (size_t t = 0; t < rows.size(); ++t) {
+    const int s = ids[rows[t]];
+    const int r = index_space != 0 ? s : perm_h[s];
+    VT_HIP(hipMemcpyAsync(&off[t], rp + r, 8, hipMemcpyDeviceToHost, st));
+  }
+  VT_HIP(hipStreamSynchronize(st));
+  std::vector<std::vector<int32_t>> ci(rows.size());
+  std::vector<std::vector<double>> cd(rows.size());
+  for (size_t t = 0; t < rows.size(); ++t) {
+    const HostCellOut& o = cells[rows[t]];
+    if (col) {
+      if ((int)o.nbr.size() <= kMaxNbr) continue;
+      std::vector<std::pair<int32_t, double>> e(o.nbr.size());
+      for (size_t k = 0; k < o.nbr.size(); ++k) e[k] = {map(o.nbr[k]), faces ? o.area[k] : 0.0};
+      std::sort(e.begin(), e.end());
+      for (const auto& x : e) {
+        ci[t].push_back(x.first);
+        cd[t].push_back(x.second);
+      }
+      VT_HIP(hipMemcpyAsync(col + off[t], ci[t].data(), ci[t].size() * 4, hipMemcpyHostToDevice, st));
+      if (faces && area) VT_HIP(hipMemcpyAsync(area + off[t], cd[t].data(), cd[t].size() * 8, hipMemcpyHostToDevice, st));
+    } else if (vxyz) {
+      if ((int)o.vplanes.size() / 3 <= kMaxVert) continue;
+      for (int32_t x : o.vplanes) ci[t].push_back(map(x));
+      VT_HIP(hipMemcpyAsync(vxyz + off[t] * 3, o.verts.data(), o.verts.size() * 8, hipMemcpyHostToDevice, st));
+      VT_HIP(hipMemcpyAsync(vplanes + off[t] * 3, ci[t].data(), ci[t].size() * 4, hipMemcpyHostToDevice, st));
+    }
+  }
+  VT_HIP(hipStreamSynchronize(st));
+  return VOTESS_OK;
+}
+
 }  // namespace
 
 extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, votess_dtype dtype, int64_t n64,
@@ -413,6 +464,14 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
   VT_HIP(hipSetDevice(ctx->device));
   votess_stats& S = out->stats;
   auto t_start = std::chrono::steady_clock::now();
+  if (P.periodic) {
+    if (P.kmodel || P.want_vertices || P.index_space != 0 || P.force_fail_every)
+      return fail(VOTESS_EINVAL, "tessellate: periodic boxes take no kmodel, vertices, sorted index space or forced "
+                                 "failures");
+    VT_TRY(tessellate_periodic(ctx, pts, dtype, n, box, P, out, st));
+    S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return VOTESS_OK;
+  }
 
   votess_grid grid;
   VT_TRY(votess_grid_plan(n, box, P.pts_per_cell, &grid));
@@ -636,6 +695,11 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     S.refined_cells = (int64_t)cnt[3];
     S.streamed_cells = (int64_t)cnt[4];
   }
+  // host-fallback cells whose rows exceed the per-cell staging (indices into
+  // long_cells / long_ids)
+  std::vector<int> long_rows;
+  std::vector<HostCellOut> long_cells;
+  std::vector<int32_t> long_ids;
   if (nhost > 0) {
     if (!P.host_fallback)
       return fail(VOTESS_EUNRESOLVED, "%d cells were not certified on the GPU and the host fallback is off", nhost);
@@ -667,23 +731,29 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
     for (int i = 0; i < nhost; ++i) {
       const HostCellOut& o = res[i];
       if (!o.ok) return fail(VOTESS_EUNRESOLVED, "host fallback could not build cell %d", ids[i]);
-      if ((int)o.nbr.size() > kMaxNbr) return fail(VOTESS_ECAPACITY, "cell %d has %zu neighbours", ids[i], o.nbr.size());
-      h_cnt[i] = (int32_t)o.nbr.size();
-      std::copy(o.nbr.begin(), o.nbr.end(), h_nbr.begin() + (size_t)i * kMaxNbr);
+      // rows longer than the per-cell staging (more than kMaxNbr neighbours
+      // or kMaxVert vertices) keep their true counts here and are written
+      // into the CSR by the host after the fill kernels (long_rows)
+      const int nnb = (int)o.nbr.size();
+      h_cnt[i] = (int32_t)nnb;
+      std::copy(o.nbr.begin(), o.nbr.begin() + std::min(nnb, kMaxNbr), h_nbr.begin() + (size_t)i * kMaxNbr);
       h_vol[i] = o.volume;
       h_st[i] = VOTESS_CELL_CERTIFIED;
       if (wantf) {
-        std::copy(o.area.begin(), o.area.end(), h_area.begin() + (size_t)i * kMaxNbr);
+        std::copy(o.area.begin(), o.area.begin() + std::min(nnb, kMaxNbr), h_area.begin() + (size_t)i * kMaxNbr);
         std::copy(o.centroid, o.centroid + 3, h_cen.begin() + (size_t)i * 3);
       }
+      const int nv = (int)o.vplanes.size() / 3;
       if (wantv) {
-        const int nv = (int)o.vplanes.size() / 3;
-        if (nv > kMaxVert) return fail(VOTESS_ECAPACITY, "cell %d has %d vertices", ids[i], nv);
         h_vc[i] = nv;
-        std::copy(o.verts.begin(), o.verts.end(), h_v.begin() + (size_t)i * kMaxVert * 3);
-        std::copy(o.vplanes.begin(), o.vplanes.end(), h_vp.begin() + (size_t)i * kMaxVert * 3);
+        std::copy(o.verts.begin(), o.verts.begin() + 3 * std::min(nv, kMaxVert), h_v.begin() + (size_t)i * kMaxVert * 3);
+        std::copy(o.vplanes.begin(), o.vplanes.begin() + 3 * std::min(nv, kMaxVert),
+                  h_vp.begin() + (size_t)i * kMaxVert * 3);
       }
+      if (nnb > kMaxNbr || (wantv && nv > kMaxVert)) long_rows.push_back(i);
     }
+    long_cells.swap(res);
+    long_ids = ids;
     for (int i = 0; i < nhost; ++i) {  // contiguous id runs go in one copy each
       int e = i;
       while (e + 1 < nhost && ids[e + 1] == ids[e] + 1) ++e;
@@ -733,6 +803,9 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
                            perm.get<int32_t>(), n, P.index_space, row_ptr.get<int64_t>(), col.get<int32_t>(),
                            volume.get<double>(), wantf ? area.get<double>() : nullptr,
                            wantf ? centroid.get<double>() : nullptr, ctx->ws, st, &nnz));
+    VT_TRY(write_long_rows(long_rows, long_cells, long_ids, perm.get<int32_t>(), n, P.index_space, wantf,
+                           row_ptr.get<int64_t>(), col.get<int32_t>(), wantf ? area.get<double>() : nullptr, nullptr,
+                           nullptr, nullptr, st));
     out->n = n;
     out->nnz = nnz;
     if (wantv) {
@@ -747,6 +820,8 @@ extern "C" votess_status votess_tessellate(votess_ctx* ctx, const void* pts, vot
       VT_TRY(launch_assemble_vertices(vcount.get<int32_t>(), verts.get<double>(), vplanes.get<int32_t>(), kMaxVert,
                                       perm.get<int32_t>(), n, P.index_space, vrow.get<int64_t>(),
                                       vxyz.get<double>(), vpl.get<int32_t>(), ctx->ws, st, &nv));
+      VT_TRY(write_long_rows(long_rows, long_cells, long_ids, perm.get<int32_t>(), n, P.index_space, false, nullptr,
+                             nullptr, nullptr, vrow.get<int64_t>(), vxyz.get<double>(), vpl.get<int32_t>(), st));
       out->nvert = nv;
       out->vrow_ptr = (int64_t*)vrow.release();
       out->vxyz = (double*)vxyz.release();

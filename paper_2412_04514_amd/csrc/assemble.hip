@@ -87,9 +87,10 @@ __global__ void k_rows_count(const int* __restrict__ nbr_count, const int* __res
 
 // One thread per row: the row's neighbour ids (mapped to the output index
 // space) are staged in LDS, column-major so that the block's threads hit
-// distinct banks, and each id goes straight to its rank in the row (ids of a
-// row are distinct), so every output is written once.  Areas move with their
-// ids; centroids with their rows.
+// distinct banks, and each id goes straight to its rank in the row (equal
+// ids, which a periodic row may hold, are ranked by position), so every
+// output is written once.  Areas move with their ids; centroids with their
+// rows.
 constexpr int kFillBlock = 64;
 template <int MAXN>
 __global__ __launch_bounds__(kFillBlock) void k_rows_fill(
@@ -105,14 +106,20 @@ __global__ __launch_bounds__(kFillBlock) void k_rows_fill(
   volume[r] = vol_sorted[s];
   if (centroid)
     for (int a = 0; a < 3; ++a) centroid[(size_t)r * 3 + a] = cen_sorted[(size_t)s * 3 + a];
-  const int cnt = min(nbr_count[s], max_nbr);
+  // a row longer than the staging stride (a host-fallback cell) is written
+  // by the host
+  if (nbr_count[s] > max_nbr) return;
+  const int cnt = nbr_count[s];
   const int* src = nbr + (size_t)s * max_nbr;
   for (int e = 0; e < cnt; ++e) ids[e * kFillBlock + tid] = sorted_space ? src[e] : perm[src[e]];
   const long long o = row_ptr[r];
   for (int e = 0; e < cnt; ++e) {
     const int v = ids[e * kFillBlock + tid];
     int rank = 0;
-    for (int x = 0; x < cnt; ++x) rank += ids[x * kFillBlock + tid] < v;
+    for (int x = 0; x < cnt; ++x) {
+      const int w = ids[x * kFillBlock + tid];
+      rank += w < v || (w == v && x < e);
+    }
     col[o + rank] = v;
     if (area) area[o + rank] = area_sorted[(size_t)s * max_nbr + e];
   }
@@ -134,6 +141,7 @@ __global__ void k_vrows_fill(const int* __restrict__ vcount, const double* __res
   const int r = sorted_space ? s : perm[s];
   const long long o = vrow_ptr[r];
   const int cnt = vcount[s];
+  if (cnt > max_vert) return;  // written by the host (a host-fallback cell)
   for (int e = 0; e < cnt; ++e) {
     const size_t si = ((size_t)s * max_vert + e) * 3;
     for (int a = 0; a < 3; ++a) {

@@ -65,6 +65,7 @@ struct ClipArgs {
   int* vplanes;
   double* area;      // [rows, max_nbr] next to nbr (nullable)
   double* centroid;  // [rows, 3] (nullable)
+  double* r2out;     // [rows] (nullable): R^2 of the certified cell (an upper bound on the float path)
   unsigned long long* counters;
   // stream phase (cells the list did not certify keep clipping by grid rings)
   int stream;
@@ -1319,6 +1320,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       a.centroid[(size_t)row * 3 + 2] = ok ? cmz : 0.0;
     }
     if (a.kneeded) a.kneeded[row] = kneed;
+    if (a.r2out) a.r2out[row] = fin == VOTESS_CELL_CERTIFIED ? (RECHECK ? (double)R2hi : (double)R2) : 0.0;
     if (a.vcount) a.vcount[row] = fin == VOTESS_CELL_CERTIFIED ? vtot : 0;
     if (a.counters) {
       if (nrecheck) atomicAdd(&a.counters[0], (unsigned long long)nrecheck);
@@ -1371,6 +1373,7 @@ votess_status launch_clip(const ClipLaunch& a, hipStream_t st) {
   c.vplanes = a.vplanes;
   c.area = a.area;
   c.centroid = a.centroid;
+  c.r2out = a.r2out;
   c.counters = a.counters;
   c.stream = a.stream;
   c.cell_start = a.cell_start;

@@ -296,6 +296,7 @@ void one_cell(const T* rec, int n, const HostGrid& G, int s, bool want_vertices,
     if (rho > 0.0 && rho * rho > 4.0 * r2) break;
   }
   out.volume = C.volume();
+  out.r2 = r2;
   std::vector<char> used(C.pl.size(), 0);
   for (const auto& t : C.tri)
     for (int e = 0; e < 3; ++e) used[t[e]] = 1;

@@ -129,6 +129,7 @@ struct ClipLaunch {
   int32_t* vplanes;
   double* area = nullptr;        // [rows, max_nbr] face areas next to nbr (nullable)
   double* centroid = nullptr;    // [rows, 3] cell centroids (nullable)
+  double* r2out = nullptr;       // [rows] R^2 of each certified cell (nullable; an upper bound on the float path)
   unsigned long long* counters;  // [8]: rechecks, unresolved, capacity, refined, streamed (certified by the
                                  // stream phase), stream entries -- nullable
   int stream = 0;                // 1: uncertified cells continue by grid rings
@@ -154,6 +155,10 @@ votess_status launch_assemble_vertices(const int32_t* vcount, const double* vert
                                        int64_t* vrow_ptr, double* vxyz, int32_t* vout, Workspace& ws,
                                        hipStream_t st, int64_t* nv_h);
 
+// periodic boxes (periodic.hip): ghost-padded tessellation of the torus
+votess_status tessellate_periodic(votess_ctx* ctx, const void* pts, votess_dtype dtype, int n, const votess_box* box,
+                                  const votess_params& P, votess_result* out, hipStream_t st);
+
 // host fallback (fallback.cpp): exact cells with unbounded k on the CPU.
 struct HostCellOut {
   std::vector<int32_t> nbr;     // sorted indices of neighbours (unordered)
@@ -162,6 +167,7 @@ struct HostCellOut {
   double centroid[3] = {0.0, 0.0, 0.0};  // (want_faces)
   std::vector<double> verts;    // absolute xyz
   std::vector<int32_t> vplanes; // sorted indices or -1..-6
+  double r2 = 0.0;              // largest squared distance from the generator to a vertex
   bool ok = false;
 };
 void host_fallback_cells(const void* sorted_h, votess_dtype dt, int n, const votess_grid& grid,

@@ -564,3 +564,74 @@ def test_fused_no_list_every_cell(kind, n, prec):
     note(f"  fused {kind} {n} {prec}: max rel vol err {ve.rel.max(initial=0):.2e}; stats {st['passes']} "
          f"streamed {st['streamed_cells']} capacity {st['capacity_cells']} host {st['fallback_cells']}")
     assert not ve.viol.any()
+
+
+@pytest.mark.parametrize("m,vertices", [(100, False), (160, True)])
+def test_cell_with_more_neighbours_than_the_kernels_hold(m, vertices):
+    """A generator inside a shell of m others (Fibonacci sphere, radius 0.1,
+    jittered) has m faces: more planes than any GPU clip kernel holds, so the
+    host fallback builds the cell, and the result carries its whole row (and,
+    for m = 160, its 316 vertices, more than the per-cell vertex staging).
+    Every row, volume, face area and vertex against the oracle."""
+    rng = np.random.default_rng(m)
+    k = np.arange(m) + 0.5
+    phi = np.arccos(1 - 2 * k / m)
+    theta = np.pi * (1 + 5 ** 0.5) * k
+    shell = 0.5 + 0.1 * np.stack([np.cos(theta) * np.sin(phi), np.sin(theta) * np.sin(phi), np.cos(phi)], 1)
+    shell += 1e-4 * rng.standard_normal(shell.shape)
+    bg = rng.random((4000, 3))
+    bg = bg[np.linalg.norm(bg - 0.5, axis=1) > 0.25]
+    P = np.concatenate([[[0.5, 0.5, 0.5]], shell, bg])
+    P = P[rng.permutation(len(P))]
+    centre = int(np.nonzero(np.all(P == 0.5, axis=1))[0][0])
+    res = vt.tessellate(torch.from_numpy(P).cuda(), k0=32, vertices=vertices, faces=True)
+    orc = oracle.tessellate(P, vertices=vertices, volume_ld=True)
+    st = res.stats
+    note(f"  shell of {m}: host cells {st['fallback_cells']}, capacity cells {st['capacity_cells']}")
+    assert st["fallback_cells"] >= 1
+    rp, col = res.row_ptr.cpu().numpy(), res.col.cpu().numpy()
+    assert rp[centre + 1] - rp[centre] == m
+    assert not compare_rows(rp, col, orc)
+    assert not volume_errors(res.volume.cpu().numpy(), orc, "f64").viol.any()
+    a_g, a_o = res.area.cpu().numpy(), orc["area"]
+    assert np.all(np.abs(a_g - a_o) <= 1e-10 * np.abs(a_o) + 1e-15)
+    if vertices:
+        vrp, vx, vp = res.vrow_ptr.cpu().numpy(), res.vxyz.cpu().numpy(), res.vplanes.cpu().numpy()
+        assert vrp[centre + 1] - vrp[centre] == 2 * m - 4
+        for i in [centre] + list(range(0, len(P), 97)):
+            g = vertex_map(vrp, vx, vp, i)
+            o = vertex_map(orc["vrow_ptr"], orc["vxyz"], orc["vplanes"], i)
+            assert set(g) == set(o), i
+            for key in g:
+                assert np.max(np.abs(g[key] - o[key])) <= 1e-9, (i, key)
+
+
+@pytest.mark.parametrize("kind,n,dt,box", [
+    ("uniform", 20_000, np.float64, ((0, 0, 0), (1, 1, 1))),
+    ("cluster", 200_000, np.float32, ((0, 0, 0), (1, 1, 1))),
+    ("uniform", 5000, np.float64, ((-0.5, 0.0, 0.25), (0.5, 2.0, 0.85))),
+    ("uniform", 7, np.float64, ((0, 0, 0), (1, 1, 1))),
+    ("uniform", 1, np.float32, ((0, 0, 0), (1, 1, 1))),
+])
+def test_periodic_every_cell(kind, n, dt, box):
+    """Periodic boxes (the box a 3-torus): every cell's neighbour multiset and
+    volume against the periodic oracle, face areas too; the volumes tile the
+    box."""
+    lo, hi = np.array(box[0], float), np.array(box[1], float)
+    P = getattr(gen, kind)(n, seed=19, dtype=dt)
+    P = (lo + P.astype(np.float64) * (hi - lo)).astype(dt)
+    P = np.minimum(P, np.nextafter(hi, lo).astype(dt))  # [lo, hi)
+    res = vt.tessellate(torch.from_numpy(P).cuda(), box=box, periodic=True, faces=True)
+    orc = oracle.tessellate(P.astype(np.float64), box[0], box[1], periodic=True, volume_ld=True)
+    rp, col = res.row_ptr.cpu().numpy(), res.col.cpu().numpy()
+    bad = compare_rows(rp, col, orc)
+    assert not bad, (bad[:5], [list(col[rp[i]:rp[i + 1]]) for i in bad[:2]],
+                     [list(orc["col"][orc["row_ptr"][i]:orc["row_ptr"][i + 1]]) for i in bad[:2]])
+    ve = volume_errors(res.volume.cpu().numpy(), orc, "f64")
+    st = res.stats
+    note(f"  periodic {kind} {n}: max rel vol err {ve.rel.max():.2e}; passes {st['passes']} "
+         f"host {st['fallback_cells']} capacity {st['capacity_cells']}")
+    assert not ve.viol.any()
+    assert abs(np.sum(res.volume.cpu().numpy()) / np.prod(hi - lo) - 1.0) <= 1e-12
+    a_g, a_o = res.area.cpu().numpy(), orc["area"]
+    assert np.all(np.abs(a_g - a_o) <= 1e-9 * np.abs(a_o) + 1e-14 * np.prod(hi - lo) ** (2 / 3))

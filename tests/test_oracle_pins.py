@@ -398,3 +398,102 @@ def test_volume_ld_against_independent_long_double():
     # where the double volume drifts the cells are tiny next to the box
     big = vl > 1e-3 / len(P)
     assert np.all(drift[big] <= 1e-12)
+
+
+# ------------------------------------------------------------ periodic boxes
+
+def _periodic_rows(r):
+    return [sorted(int(x) for x in row) for row in oracle.rows(r)]
+
+
+def test_periodic_closed_forms():
+    """One point: its cell is the box, with its six own images as neighbours
+    (also in an anisotropic box); two points split along x: two slabs of
+    half the volume, each with its two images of the other point and its own
+    four y/z images; simple-cubic and BCC lattices: cubes of 1/m^3 with 6
+    neighbours and truncated octahedra of a^3 / 2 with 14, for EVERY cell."""
+    r = oracle.tessellate(np.array([[0.3, 0.4, 0.5]]), periodic=True)
+    assert r["volume"].tolist() == [1.0] and _periodic_rows(r) == [[0] * 6]
+    r = oracle.tessellate(np.array([[0.3, 0.4, 0.5]]), lo=(0, 0, 0), hi=(1, 2, 0.6), periodic=True)
+    np.testing.assert_allclose(r["volume"], [1.2], rtol=1e-15)
+    assert _periodic_rows(r) == [[0] * 6]
+    r = oracle.tessellate(np.array([[0.1, 0.5, 0.5], [0.6, 0.5, 0.5]]), periodic=True)
+    np.testing.assert_allclose(r["volume"], [0.5, 0.5], rtol=1e-15)
+    assert _periodic_rows(r) == [[0, 0, 0, 0, 1, 1], [0, 0, 1, 1, 1, 1]]
+    m = 4
+    g = (np.arange(m) + 0.25) / m
+    P = np.array(np.meshgrid(g, g, g, indexing="ij")).reshape(3, -1).T
+    r = oracle.tessellate(P, periodic=True, volume_ld=True)
+    np.testing.assert_allclose(r["volume_ld"], 1 / m ** 3, rtol=1e-14)
+    assert set(np.diff(r["row_ptr"]).tolist()) == {6}
+    a = 0.25
+    base = np.array(np.meshgrid(*[np.arange(4)] * 3, indexing="ij")).reshape(3, -1).T * a + 0.0625
+    P = np.concatenate([base, base + a / 2])
+    r = oracle.tessellate(P, periodic=True)
+    np.testing.assert_allclose(r["volume"], a ** 3 / 2, rtol=1e-13)
+    assert set(np.diff(r["row_ptr"]).tolist()) == {14}
+
+
+@pytest.mark.parametrize("kind,seed", [("uniform", 41), ("cluster", 42)])
+def test_periodic_invariants(kind, seed):
+    """Volumes tile the torus; the neighbour relation is symmetric with
+    multiplicity; translating every point by t (mod L) changes no neighbour
+    set and moves volumes by rounding only.  (FP32-rounded points and a
+    dyadic t, so that the translated set is exact in double.)"""
+    P = getattr(gen, kind)(6000, seed=seed, dtype=np.float32).astype(np.float64)
+    r = oracle.tessellate(P, periodic=True, volume_ld=True)
+    assert abs(np.sum(r["volume_ld"]) - 1.0) <= 1e-13
+    assert abs(np.sum(r["volume"]) - 1.0) <= 1e-12
+    src = np.repeat(np.arange(len(P)), np.diff(r["row_ptr"]))
+    fwd = np.sort(src * len(P) + r["col"])
+    bwd = np.sort(r["col"].astype(np.int64) * len(P) + src)
+    assert np.array_equal(fwd, bwd)
+    t = np.array([0.375, 0.125, 0.6875])
+    r2 = oracle.tessellate((P + t) % 1.0, periodic=True, volume_ld=True)
+    assert _periodic_rows(r2) == _periodic_rows(r)
+    np.testing.assert_allclose(r2["volume_ld"], r["volume_ld"], rtol=1e-11)
+
+
+def _periodic_cell_qhull(P, i, span=2):
+    """The periodic cell of point i from Qhull: the intersection of the
+    bisectors of p_i with every image p_j + m (m in {-span..span}^3, unit
+    box) -- enough for the point counts used here -- with its neighbour
+    multiset (the point index of each plane holding at least three vertices)."""
+    from scipy.spatial import ConvexHull, HalfspaceIntersection
+    rng = range(-span, span + 1)
+    shifts = np.array([(a, b, c) for a in rng for b in rng for c in rng], dtype=np.float64)
+    Q = (P[None, :, :] + shifts[:, None, :]).reshape(-1, 3)
+    owner = np.tile(np.arange(len(P)), len(shifts))
+    keep = np.any(Q != P[i], axis=1)
+    Q, owner = Q[keep], owner[keep]
+    ns = Q - P[i]
+    cs = 0.5 * np.sum(ns ** 2, axis=1)
+    H = HalfspaceIntersection(np.hstack([ns, -cs[:, None]]), np.zeros(3))
+    vol = ConvexHull(H.intersections).volume
+    act = np.abs(H.intersections @ ns.T - cs) <= 1e-9 * np.linalg.norm(ns, axis=1)
+    faces = sorted(int(owner[f]) for f in np.nonzero(act.sum(0) >= 3)[0])
+    return vol, faces
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_periodic_against_all_images(seed):
+    """Every cell of a small periodic set against Qhull over all images within
+    two periods: volumes and neighbour multisets."""
+    rng = np.random.default_rng(500 + seed)
+    n = [3, 5, 8, 13, 21, 34][seed % 6]
+    P = rng.random((n, 3))
+    r = oracle.tessellate(P, periodic=True)
+    rows = _periodic_rows(r)
+    for i in range(n):
+        vol, faces = _periodic_cell_qhull(P, i)
+        assert abs(vol - r["volume"][i]) <= 1e-10 * vol
+        assert faces == rows[i], (seed, i)
+
+
+def test_periodic_poisson_voronoi_mean_faces():
+    """With no boundary every cell counts: the mean face count of a Poisson-
+    Voronoi tessellation, 2 + 48 pi^2 / 35 = 15.535 (Meijering)."""
+    P = gen.uniform(40_000, seed=43, dtype=np.float64)
+    r = oracle.tessellate(P, periodic=True)
+    mean = np.diff(r["row_ptr"]).mean()
+    assert abs(mean - (2 + 48 * np.pi ** 2 / 35)) <= 0.06, mean
