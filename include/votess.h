@@ -324,6 +324,20 @@ VOTESS_API votess_status votess_features(votess_ctx* ctx, const void* sorted, in
                               const int32_t* cell_start, const int32_t* subinfo, const int32_t* sub_start,
                               const int32_t* queries, int64_t nq, float* feats, void* stream);
 
+/* The same features as votess_features, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the 16-NN lists live in a static device
+ * array of the library (votess_features_noalloc_max() queries, 4 MiB per
+ * device, held until the process ends), so the call allocates nothing.
+ * nq above that maximum is EINVAL.  Every call on a device shares that
+ * device's array: calls that overlap on one GPU (different streams or
+ * threads) race.  Enqueued on `stream`; does not synchronise. */
+VOTESS_API int64_t votess_features_noalloc_max(void);
+VOTESS_API votess_status votess_features_noalloc(votess_ctx* ctx, const void* sorted, int64_t n,
+                                                 const votess_grid* grid, const int32_t* cell_start,
+                                                 const int32_t* subinfo, const int32_t* sub_start,
+                                                 const int32_t* queries, int64_t nq, float* feats, void* stream);
+
 /* logits [nq,7] float = network(standardised feats). */
 VOTESS_API votess_status votess_kmodel_forward(votess_kmodel* m, const float* feats, int64_t nq, float* logits, void* stream);
 

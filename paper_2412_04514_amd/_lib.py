@@ -103,6 +103,8 @@ SIGNATURES = {
     "votess_kmodel_grad": (C.c_int, [P, P, P, i64, P, P, P]),
     "votess_kmodel_train_step": (C.c_int, [P, P, P, i64, C.c_float, P, P]),
     "votess_kmodel_choose": (C.c_int, [P, P, i64, C.c_float, P, P]),
+    "votess_features_noalloc_max": (i64, []),
+    "votess_features_noalloc": (C.c_int, [P, P, i64, C.POINTER(Grid), P, P, P, P, i64, P, P]),
     "votess_kmodel_labels": (C.c_int, [P, P, P, i64, P, P]),
     "votess_kmodel_fit_norm": (C.c_int, [P, P, i64, P]),
     "votess_kmodel_blob_size": (C.c_size_t, []),

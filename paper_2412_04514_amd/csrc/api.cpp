@@ -163,6 +163,10 @@ votess_ctx* votess_create(int device) {
     votess_destroy(ctx);
     return nullptr;
   }
+  if (init_noalloc_scratch(ctx) != VOTESS_OK) {
+    votess_destroy(ctx);
+    return nullptr;
+  }
   return ctx;
 }
 

@@ -72,12 +72,16 @@ struct votess_ctx {
   int* d_counter = nullptr;    // small device scratch counters [16]
   votess::Workspace ws;
   int num_cu = 0;
+  void* noalloc_scratch = nullptr;  // device address of the static scratch (votess_features_noalloc)
 };
 
 namespace votess {
 
 void* dev_alloc(votess_ctx* ctx, size_t bytes);
 void dev_free(votess_ctx* ctx, void* p);
+// looks up the device address of the allocation-free pass's static scratch
+// on the context's (current) device (learned.hip)
+votess_status init_noalloc_scratch(votess_ctx* ctx);
 
 // --------------------------------------------------------------- launchers
 // grid sort (grid_sort.hip)

@@ -686,6 +686,27 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
 
 }  // namespace votess
 
+// ------------------------------------------- allocation-free feature pass
+// Scratch of votess_features_noalloc: the 16-NN lists of at most
+// kNoAllocMaxQ queries (4 MiB), held by every device the library runs on
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it is only a stand-in for the symbol): the device
+// address is looked up once per context (votess_create, with the context's
+// device current) and kept in ctx->noalloc_scratch.
+constexpr int64_t kNoAllocMaxQ = 65536;
+static __device__ __align__(256) int32_t scratch[kNoAllocMaxQ * 16];
+
+namespace votess {
+votess_status init_noalloc_scratch(votess_ctx* ctx) {
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(VOTESS_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+  ctx->noalloc_scratch = p;
+  return VOTESS_OK;
+}
+}  // namespace votess
+
 // ------------------------------------------------------------------ C ABI
 using namespace votess;
 
@@ -800,6 +821,28 @@ votess_status votess_features(votess_ctx* ctx, const void* sorted, int64_t n, co
   (void)hipStreamSynchronize(st);
   dev_free(ctx, knn16);
   return rc;
+}
+
+int64_t votess_features_noalloc_max(void) { return kNoAllocMaxQ; }
+
+votess_status votess_features_noalloc(votess_ctx* ctx, const void* sorted, int64_t n, const votess_grid* grid,
+                                      const int32_t* cell_start, const int32_t* subinfo, const int32_t* sub_start,
+                                      const int32_t* queries, int64_t nq, float* feats, void* stream) {
+  if (!ctx || !grid) return fail(VOTESS_EINVAL, "features_noalloc: null ctx/grid");
+  if (!queries) nq = n;
+  if (n < 1 || nq < 0 || n >= (1LL << 31) - 1) return fail(VOTESS_EINVAL, "features_noalloc: bad sizes");
+  if (nq > kNoAllocMaxQ)
+    return fail(VOTESS_EINVAL, "features_noalloc: %lld queries exceed the static scratch (at most %lld)",
+                (long long)nq, (long long)kNoAllocMaxQ);
+  if (nq > 0 && (!sorted || !cell_start || !feats)) return fail(VOTESS_EINVAL, "features_noalloc: null buffer");
+  VT_TRY(check_sub(subinfo, sub_start, n, "features_noalloc"));
+  if (!ctx->noalloc_scratch) return fail(VOTESS_EHIP, "features_noalloc: scratch address not set up");
+  VT_HIP(hipSetDevice(ctx->device));
+  SubGrid sg;
+  sg.info = (const int2*)subinfo;
+  sg.start = sub_start;
+  return run_features(ctx, sorted, VOTESS_F32, (int)n, to_dev(*grid), cell_start, sg, queries, (int)nq,
+                      (int32_t*)ctx->noalloc_scratch, feats, (hipStream_t)stream);
 }
 
 votess_status votess_kmodel_forward(votess_kmodel* km, const float* feats, int64_t nq, float* logits, void* stream) {
