@@ -262,7 +262,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   const int g = lane / L, j = lane % L;
   const int gb = g * L;
   const int vb = g * TP, pb = g * PMAX;
-  const long long t_idx = (long long)blockIdx.x * G + g;
+  // XCD-aware block order (blocks are dealt round-robin over the eight XCDs):
+  // launched block b clips logical block (b mod 8) per + b / 8, so each XCD
+  // takes a contiguous stretch of grid-sorted cells, whose neighbours its L2
+  // then holds
+  const int nblk = (a.nc + G - 1) / G, per = (nblk + 7) / 8;
+  const int lblk = (int)(blockIdx.x % 8u) * per + (int)(blockIdx.x / 8u);
+  if (lblk >= nblk) return;  // the whole (one-wave) block
+  const long long t_idx = (long long)lblk * G + g;
   const bool have = t_idx < a.nc;
   const int sid = have ? (a.cells ? a.cells[t_idx] : (int)t_idx) : 0;
   const int row = a.out_by_id ? sid : (int)t_idx;
@@ -1334,7 +1341,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
 template <typename P, typename R, int L, int TMAX, int PMAX, bool RECHECK>
 votess_status run(const ClipArgs& ca, hipStream_t st) {
   constexpr int G = 64 / L;
-  const unsigned blocks = (unsigned)((ca.nc + G - 1) / G);
+  const unsigned blocks = (unsigned)(8 * (((ca.nc + G - 1) / G + 7) / 8));
   if (ca.stream)
     k_clip<P, R, L, TMAX, PMAX, RECHECK, true><<<blocks, 64, 0, st>>>(ca);
   else

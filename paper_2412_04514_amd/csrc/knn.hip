@@ -125,18 +125,26 @@ struct GroupList {
 
 // Held to 5 waves per SIMD (96 VGPRs, ~100 bytes per lane of spills): the
 // search is latency-bound, and the fifth wave measured ~8% faster than four.
+// Blocks are taken in an XCD-aware order: the hardware deals launched
+// blocks round-robin over the eight XCDs, so launched block b runs logical
+// block (b mod 8) per + b / 8 (per = blocks / 8, rounded up; the launch is
+// padded to 8 per) and each XCD works on one contiguous stretch of the
+// grid-sorted queries, whose candidates its own L2 then holds.
 template <typename T, typename D, int K, int GS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_knn(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
                                              const int* __restrict__ cell_start, SubGrid sub,
                                              const int* __restrict__ queries, int nq, int* __restrict__ knn,
-                                             unsigned* __restrict__ err) {
+                                             unsigned* __restrict__ err, int nblocks) {
   constexpr int E = K / GS;
   static_assert(E * GS == K, "K must be a multiple of GS");
   using O = KeyOps<D>;
   using Key = typename O::Key;
+  const int per = (nblocks + 7) / 8;
+  const int lb = (int)(blockIdx.x % 8u) * per + (int)(blockIdx.x / 8u);
+  if (lb >= nblocks) return;
   const int lane = threadIdx.x & 63;
   const int l = lane & (GS - 1), gb = lane - l;
-  const int q = (int)((blockIdx.x * blockDim.x + threadIdx.x) / GS);
+  const int q = (int)(((long long)lb * blockDim.x + threadIdx.x) / GS);
   if (q >= nq) return;  // whole groups leave together
   const int s = queries ? queries[q] : q;
   const auto pr = rec[s];
@@ -354,217 +362,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   if (l == 0 && O::finite(L.key[0]) && O::d2(L.key[0]) == 0.0) atomicOr(err, ERR_DUPLICATE);
 }
 
-// Batched form for lists of up to 64 (K padded to the group width G = KP, a
-// power of two): lane l of the group holds the l-th key of the ascending
-// list.  Candidates come G at a time (one per lane, one coalesced load); a
-// round in which some candidate beats the list's K-th key is merged in one
-// step -- the round is sorted by a bitonic network across the lanes, turned
-// around, and min'ed against the list (the G smallest of both, as a bitonic
-// sequence), which a bitonic merge sorts again -- instead of one insertion per
-// candidate.  Keys are distinct (the index is part of the key), so the list
-// is the same as one built by insertions.  Rounds whose candidates all lose
-// cost one ballot.  Blocks are remapped so that each XCD (blocks dispatched
-// round-robin over the eight of them) works on one contiguous stretch of the
-// grid-sorted queries and its L2 sees their shared candidates.
-template <typename T, typename D, int K, int G>
-__global__ __launch_bounds__(256) void k_knn_batch(const typename Rec<T>::type* __restrict__ rec, int n, GridDev Gd,
-                                                   const int* __restrict__ cell_start, SubGrid sub,
-                                                   const int* __restrict__ queries, int nq, int* __restrict__ knn,
-                                                   unsigned* __restrict__ err, int nblocks) {
-  static_assert((G & (G - 1)) == 0 && G <= 64 && K <= G, "group width: a power of two, at least K");
-  using O = KeyOps<D>;
-  using Key = typename O::Key;
-  // XCD-aware block order: launched blocks b = 0 .. 8 per - 1, logical block
-  // (b mod 8) per + b / 8
-  const int per = (nblocks + 7) / 8;
-  const int lb = (int)(blockIdx.x % 8u) * per + (int)(blockIdx.x / 8u);
-  if (lb >= nblocks) return;
-  const int lane = threadIdx.x & 63;
-  const int l = lane & (G - 1), gb = lane - l;
-  const int q = (int)(((long long)lb * blockDim.x + threadIdx.x) / G);
-  if (q >= nq) return;  // whole groups leave together
-  const int s = queries ? queries[q] : q;
-  const auto pr = rec[s];
-  const D px = (D)pr.x, py = (D)pr.y, pz = (D)pr.z;
-  const int cx = axis_cell((double)pr.x, Gd.lo0, Gd.ih0, Gd.g0);
-  const int cy = axis_cell((double)pr.y, Gd.lo1, Gd.ih1, Gd.g1);
-  const int cz = axis_cell((double)pr.z, Gd.lo2, Gd.ih2, Gd.g2);
-  const double ext = fmax(Gd.hi0 - Gd.lo0, fmax(Gd.hi1 - Gd.lo1, Gd.hi2 - Gd.lo2));
-  const double margin = 1e-9 * ext;  // covers floor() rounding at cell borders
-  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-
-  Key key = O::inf();  // this lane's entry of the list
-  Key wk = O::inf();   // the list's K-th key (group-uniform)
-  auto kmin = [&](const Key& a, const Key& b) { return O::pick(O::less(b, a), b, a); };
-  auto kmax = [&](const Key& a, const Key& b) { return O::pick(O::less(b, a), a, b); };
-
-  // candidates [jb, je), G at a time
-  auto scan = [&](int jb, int je) {
-    for (int base = jb; base < je; base += G) {
-      const int j = base + l;
-      Key c = O::inf();
-      if (j < je && j != s) {
-        const auto qr = rec[j];
-        c = O::make(dist2_nc((D)qr.x - px, (D)qr.y - py, (D)qr.z - pz), j);
-        if (!O::less(c, wk)) c = O::inf();
-      }
-      if (((__ballot(O::finite(c)) >> gb) & gmask) == 0ull) continue;
-      // sort the round ascending across the group
-#pragma unroll
-      for (int ks = 2; ks <= G; ks <<= 1) {
-#pragma unroll
-        for (int js = ks >> 1; js > 0; js >>= 1) {
-          const Key o = O::shfl_xor(c, js);
-          const bool keep_min = ((l & ks) == 0) == ((l & js) == 0);
-          c = O::pick(keep_min, kmin(c, o), kmax(c, o));
-        }
-      }
-      // the G smallest of list and round, as a bitonic sequence, then sorted
-      const Key rev = O::shfl(c, gb + (G - 1 - l));
-      key = kmin(key, rev);
-#pragma unroll
-      for (int js = G >> 1; js > 0; js >>= 1) {
-        const Key o = O::shfl_xor(key, js);
-        key = O::pick((l & js) == 0, kmin(key, o), kmax(key, o));
-      }
-      wk = O::shfl(key, gb + K - 1);
-    }
-  };
-  auto rad2 = [&]() { return O::d2(wk) * (1.0 + 1e-6); };
-  auto gap = [&](double p, double a_, double b_) { return fmax(0.0, fmax(a_ - p, p - b_) - margin); };
-  const double p0 = (double)pr.x, p1 = (double)pr.y, p2 = (double)pr.z;
-
-  // ---- phase A: a seed block around the query holding at least K other
-  // points (from the cell / sub-cell starts), scanned whole
-  const int c0 = cx + Gd.g0 * (cy + Gd.g1 * cz);
-  const int2 info0 = sub.info ? sub.info[c0] : make_int2(-1, 0);
-  const bool seed_sub = info0.x >= 0 && cell_start[c0 + 1] - cell_start[c0] >= K + 1;
-  int bx0, bx1, by0, by1, bz0, bz1;
-  if (seed_sub) {
-    const int* srec = sub.start + info0.x;
-    const SubCell sc = sub_cell(srec);
-    const int base0 = cell_start[c0];
-    const int qx = sub_axis(p0, sc.lo0, sc.ih0, sc.m0), qy = sub_axis(p1, sc.lo1, sc.ih1, sc.m1),
-              qz = sub_axis(p2, sc.lo2, sc.ih2, sc.m2);
-    for (int rs = 0;; ++rs) {
-      bx0 = max(qx - rs, 0); bx1 = min(qx + rs, sc.m0 - 1);
-      by0 = max(qy - rs, 0); by1 = min(qy + rs, sc.m1 - 1);
-      bz0 = max(qz - rs, 0); bz1 = min(qz + rs, sc.m2 - 1);
-      int cnt = 0;
-      for (int z = bz0; z <= bz1; ++z)
-        for (int y = by0; y <= by1; ++y) {
-          const int row = kSubHead + sc.m0 * (y + sc.m1 * z);
-          cnt += srec[row + bx1 + 1] - srec[row + bx0];
-        }
-      if (cnt >= K + 1 || (bx0 == 0 && by0 == 0 && bz0 == 0 && bx1 == sc.m0 - 1 && by1 == sc.m1 - 1 &&
-                           bz1 == sc.m2 - 1))
-        break;
-    }
-    for (int z = bz0; z <= bz1; ++z)
-      for (int y = by0; y <= by1; ++y) {
-        const int row = kSubHead + sc.m0 * (y + sc.m1 * z);
-        scan(base0 + srec[row + bx0], base0 + srec[row + bx1 + 1]);
-      }
-  } else {
-    for (int r = 0;; ++r) {
-      bx0 = max(cx - r, 0); bx1 = min(cx + r, Gd.g0 - 1);
-      by0 = max(cy - r, 0); by1 = min(cy + r, Gd.g1 - 1);
-      bz0 = max(cz - r, 0); bz1 = min(cz + r, Gd.g2 - 1);
-      int cnt = 0;
-      for (int z = bz0; z <= bz1; ++z)
-        for (int y = by0; y <= by1; ++y) {
-          const int row = Gd.g0 * (y + Gd.g1 * z);
-          cnt += cell_start[row + bx1 + 1] - cell_start[row + bx0];
-        }
-      if (cnt >= K + 1 || (bx0 == 0 && by0 == 0 && bz0 == 0 && bx1 == Gd.g0 - 1 && by1 == Gd.g1 - 1 &&
-                           bz1 == Gd.g2 - 1))
-        break;
-    }
-    for (int z = bz0; z <= bz1; ++z)
-      for (int y = by0; y <= by1; ++y) {
-        const int row = Gd.g0 * (y + Gd.g1 * z);
-        scan(cell_start[row + bx0], cell_start[row + bx1 + 1]);
-      }
-  }
-
-  // ---- phase B: every other grid cell / sub-cell row that meets the ball of
-  // the list's K-th distance (re-cut to the shrinking ball row by row)
-  auto scan_dense = [&](int c, int ccx, int ccy, int ccz, bool own) {
-    const int* drec = sub.start + sub.info[c].x;
-    const SubCell sc = sub_cell(drec);
-    const int base = cell_start[c];
-    const double w1 = 1.0 / sc.ih1, w2 = 1.0 / sc.ih2;
-    const double ylo = Gd.lo1 + ccy * Gd.h1, yhi = ylo + Gd.h1, zlo = Gd.lo2 + ccz * Gd.h2, zhi = zlo + Gd.h2;
-    const double rz = sqrt(rad2()) + margin;
-    const int sz0 = sub_axis(p2 - rz, sc.lo2, sc.ih2, sc.m2), sz1 = sub_axis(p2 + rz, sc.lo2, sc.ih2, sc.m2);
-    for (int sz = sz0; sz <= sz1; ++sz) {
-      const double za = sz == 0 ? zlo : sc.lo2 + sz * w2, zb = sz == sc.m2 - 1 ? zhi : sc.lo2 + (sz + 1) * w2;
-      const double gz = gap(p2, za, zb);
-      const double remz = rad2() - gz * gz;
-      if (remz < 0.0) continue;
-      const double ry = sqrt(remz) + margin;
-      const int sy0 = sub_axis(p1 - ry, sc.lo1, sc.ih1, sc.m1), sy1 = sub_axis(p1 + ry, sc.lo1, sc.ih1, sc.m1);
-      for (int sy = sy0; sy <= sy1; ++sy) {
-        const double ya = sy == 0 ? ylo : sc.lo1 + sy * w1, yb = sy == sc.m1 - 1 ? yhi : sc.lo1 + (sy + 1) * w1;
-        const double gy = gap(p1, ya, yb);
-        const double rem = rad2() - gz * gz - gy * gy;
-        if (rem < 0.0) continue;
-        const double rx = sqrt(rem) + margin;
-        int sx0 = sub_axis(p0 - rx, sc.lo0, sc.ih0, sc.m0), sx1 = sub_axis(p0 + rx, sc.lo0, sc.ih0, sc.m0);
-        const int row = kSubHead + sc.m0 * (sy + sc.m1 * sz);
-        if (own && sy >= by0 && sy <= by1 && sz >= bz0 && sz <= bz1) {
-          if (sx0 < bx0) scan(base + drec[row + sx0], base + drec[row + min(sx1, bx0 - 1) + 1]);
-          sx0 = max(sx0, bx1 + 1);
-        }
-        if (sx0 <= sx1) scan(base + drec[row + sx0], base + drec[row + sx1 + 1]);
-      }
-    }
-  };
-  if (O::finite(wk)) {
-    const double rz = sqrt(rad2()) + margin;
-    const int gz0 = axis_cell(p2 - rz, Gd.lo2, Gd.ih2, Gd.g2), gz1 = axis_cell(p2 + rz, Gd.lo2, Gd.ih2, Gd.g2);
-    for (int z = gz0; z <= gz1; ++z) {
-      const double gz = gap(p2, Gd.lo2 + z * Gd.h2, Gd.lo2 + (z + 1) * Gd.h2);
-      const double remz = rad2() - gz * gz;
-      if (remz < 0.0) continue;
-      const double ry = sqrt(remz) + margin;
-      const int gy0 = axis_cell(p1 - ry, Gd.lo1, Gd.ih1, Gd.g1), gy1 = axis_cell(p1 + ry, Gd.lo1, Gd.ih1, Gd.g1);
-      for (int y = gy0; y <= gy1; ++y) {
-        const double gy = gap(p1, Gd.lo1 + y * Gd.h1, Gd.lo1 + (y + 1) * Gd.h1);
-        const double rem = rad2() - gz * gz - gy * gy;
-        if (rem < 0.0) continue;
-        const double rx = sqrt(rem) + margin;
-        const int x0 = axis_cell(p0 - rx, Gd.lo0, Gd.ih0, Gd.g0), x1 = axis_cell(p0 + rx, Gd.lo0, Gd.ih0, Gd.g0);
-        const int row = Gd.g0 * (y + Gd.g1 * z);
-        const bool in_seed = !seed_sub && y >= by0 && y <= by1 && z >= bz0 && z <= bz1;
-        int x = x0;
-        while (x <= x1) {
-          if (in_seed && x >= bx0 && x <= bx1) {
-            x = bx1 + 1;
-            continue;
-          }
-          const int lim = (in_seed && x < bx0) ? min(x1, bx0 - 1) : x1;
-          int xe = x;
-          if (sub.info) {
-            while (xe <= lim && sub.info[row + xe].x < 0) ++xe;
-          } else {
-            xe = lim + 1;
-          }
-          if (xe > x) {
-            scan(cell_start[row + x], cell_start[row + xe]);
-            x = xe;
-            continue;
-          }
-          scan_dense(row + x, x, y, z, seed_sub && row + x == c0);
-          ++x;
-        }
-      }
-    }
-  }
-  if (l < K) knn[(size_t)q * K + l] = O::idx(key);
-  if (l == 0 && O::finite(key) && O::d2(key) == 0.0) atomicOr(err, ERR_DUPLICATE);
-}
-
 template <typename T, typename D>
 votess_status dispatch_k(int k, const void* sorted, int n, const GridDev& G, const int32_t* cs, const SubGrid& sub,
                          const int32_t* qs, int nq, int32_t* knn, unsigned* err, hipStream_t st) {
@@ -572,32 +369,25 @@ votess_status dispatch_k(int k, const void* sorted, int n, const GridDev& G, con
   const R4* rec = (const R4*)sorted;
 #define VT_KNN_CASE(KK, GG)                                                                 \
   case KK: {                                                                                \
-    const unsigned blocks = (unsigned)(((long long)nq * GG + 255) / 256);                   \
-    k_knn<T, D, KK, GG><<<blocks, 256, 0, st>>>(rec, n, G, cs, sub, qs, nq, knn, err);      \
-    break;                                                                                  \
-  }
-#define VT_KNN_BATCH(KK, GG)                                                                \
-  case KK: {                                                                                \
     const int blocks = (int)(((long long)nq * GG + 255) / 256);                             \
     const unsigned launched = (unsigned)(8 * ((blocks + 7) / 8));                           \
-    k_knn_batch<T, D, KK, GG><<<launched, 256, 0, st>>>(rec, n, G, cs, sub, qs, nq, knn, err, blocks); \
+    k_knn<T, D, KK, GG><<<launched, 256, 0, st>>>(rec, n, G, cs, sub, qs, nq, knn, err, blocks); \
     break;                                                                                  \
   }
   switch (k) {
-    VT_KNN_BATCH(8, 8)
-    VT_KNN_BATCH(12, 16)
-    VT_KNN_BATCH(16, 16)
-    VT_KNN_BATCH(24, 32)
-    VT_KNN_BATCH(32, 32)
-    VT_KNN_BATCH(48, 64)
-    VT_KNN_BATCH(64, 64)
+    VT_KNN_CASE(8, 4)
+    VT_KNN_CASE(12, 4)
+    VT_KNN_CASE(16, 4)
+    VT_KNN_CASE(24, 8)
+    VT_KNN_CASE(32, 8)
+    VT_KNN_CASE(48, 16)
+    VT_KNN_CASE(64, 8)
     VT_KNN_CASE(128, 16)
     VT_KNN_CASE(256, 32)
     default:
       return fail(VOTESS_EINVAL, "knn: k=%d has no kernel (k must be one of 8,12,16,24,32,48,64,128,256)", k);
   }
 #undef VT_KNN_CASE
-#undef VT_KNN_BATCH
   VT_HIP(hipGetLastError());
   return VOTESS_OK;
 }
