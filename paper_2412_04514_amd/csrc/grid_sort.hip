@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void k_order_dense(const typename Rec<T>::type
   __shared__ int s_cnt[kCntLds];
   __shared__ double sbox[4][6];
   __shared__ int shist[3][kSubBins];
-  __shared__ int soff, sm[3], s_crowd;
+  __shared__ int soff, sm[3], s_crowd, s_bin[3][2];
   __shared__ double slo[3], sih[3];
   const int nb = *nbig;
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -433,22 +433,39 @@ __global__ __launch_bounds__(256) void k_order_dense(const typename Rec<T>::type
       }
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
-      const int a = threadIdx.x;
-      const double lo = sbox[0][a], w = sbox[0][3 + a] - lo;
+    {
+      // the box of the central 90% per axis: the first bin whose inclusive
+      // prefix count exceeds len/20, and the first that reaches len - len/20,
+      // found from a block-wide prefix scan (four bins per thread)
+      static_assert(kSubBins == 4 * 256, "four histogram bins per thread");
       const int cut_lo = len / 20, cut_hi = len - len / 20;
-      int acc = 0, blo = 0, bhi = kSubBins - 1;
-      bool got_lo = false;
-      for (int i = 0; i < kSubBins; ++i) {
-        const int next = acc + shist[a][i];
-        if (!got_lo && next > cut_lo) { blo = i; got_lo = true; }
-        if (next >= cut_hi) { bhi = i; break; }
-        acc = next;
+      for (int a = 0; a < 3; ++a) {
+        int v[4], sum = 0;
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+          v[k2] = shist[a][threadIdx.x * 4 + k2];
+          sum += v[k2];
+        }
+        int tot;
+        int run = block_excl_scan<int>(sum, &tot);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+          const int prev = run;
+          run += v[k2];
+          if (prev <= cut_lo && run > cut_lo) s_bin[a][0] = (int)threadIdx.x * 4 + k2;
+          if (prev < cut_hi && run >= cut_hi) s_bin[a][1] = (int)threadIdx.x * 4 + k2;
+        }
       }
-      slo[a] = lo + w * ((double)blo / kSubBins);
-      sih[a] = fmax(w * ((double)(bhi + 1 - blo) / kSubBins), (a == 0 ? G.h0 : a == 1 ? G.h1 : G.h2) * 0x1p-30);
+      __syncthreads();
+      if (threadIdx.x < 3) {
+        const int a = threadIdx.x;
+        const double lo = sbox[0][a], w = sbox[0][3 + a] - lo;
+        const int blo = s_bin[a][0], bhi = s_bin[a][1];
+        slo[a] = lo + w * ((double)blo / kSubBins);
+        sih[a] = fmax(w * ((double)(bhi + 1 - blo) / kSubBins), (a == 0 ? G.h0 : a == 1 ? G.h1 : G.h2) * 0x1p-30);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x == 0) {
       const double e0 = sih[0], e1 = sih[1], e2 = sih[2];  // extents here
       int m0, m1, m2;

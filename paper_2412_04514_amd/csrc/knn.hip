@@ -172,15 +172,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   const unsigned long long gmask = (GS == 64) ? ~0ull : ((1ull << GS) - 1ull);
 
   // candidates [jb, je), GS at a time; each that beats the k-th is inserted
+  // with float keys the records of a batch are loaded one batch ahead, so
+  // that their latency overlaps the previous batch's ranking and insertions
+  // (with (double, index) keys the extra registers cost more than it saves)
+  constexpr bool kPrefetch = sizeof(Key) == 8;
   auto scan = [&](int jb, int je) {
+    auto nxt = rec[jb + l < je ? jb + l : s];
     for (int base = jb; base < je; base += GS) {
       const int j = base + l;
+      const auto qr = kPrefetch ? nxt : rec[j < je ? j : s];
+      if (kPrefetch && base + GS < je) nxt = rec[base + GS + l < je ? base + GS + l : s];
       Key ck = O::inf();
       const bool valid = j < je && j != s;
-      if (valid) {
-        const auto qr = rec[j];
-        ck = O::make(dist2_nc((D)qr.x - px, (D)qr.y - py, (D)qr.z - pz), j);
-      }
+      if (valid) ck = O::make(dist2_nc((D)qr.x - px, (D)qr.y - py, (D)qr.z - pz), j);
       bool pass;
       if (kSortFill && filling) {
         const unsigned long long vm = (__ballot(valid) >> gb) & gmask;
@@ -341,7 +345,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
           const int lim = (in_seed && x < bx0) ? min(x1, bx0 - 1) : x1;
           int xe = x;
           if (sub.info) {
-            while (xe <= lim && sub.info[row + xe].x < 0) ++xe;
+            // the stretch of cells without sub-grids: the group reads GS
+            // consecutive cells' records at once and ends it at the first
+            // dense one
+            for (;;) {
+              const int xc = xe + l;
+              const bool dense = xc <= lim && sub.info[row + xc].x >= 0;
+              const unsigned long long dm = (__ballot(dense) >> gb) & gmask;
+              if (dm) {
+                xe += __ffsll((long long)dm) - 1;
+                break;
+              }
+              xe += GS;
+              if (xe > lim) {
+                xe = lim + 1;
+                break;
+              }
+            }
           } else {
             xe = lim + 1;
           }
