@@ -17,14 +17,22 @@ __device__ __forceinline__ int cell_of(double x, double y, double z, const GridD
   return axis_cell(x, G.lo0, G.ih0, G.g0) + G.g0 * (axis_cell(y, G.lo1, G.ih1, G.g1) + G.g1 * axis_cell(z, G.lo2, G.ih2, G.g2));
 }
 
-// Squared distance with no fused multiply-add, so every kernel that ranks
-// points by it (k-NN lists, the clip's list and stream phases) computes the
-// same value.
+// Squared distance with every product and sum rounded on its own, so every
+// kernel that ranks points by it (k-NN lists, the clip's list and stream
+// phases) computes the same bits: the clip tells a list member from a later
+// candidate of equal distance by comparing these values exactly.  Contraction
+// is switched off here rather than relying on __fmul_rn / __fadd_rn, which
+// HIP defines as the plain operators: those fuse into FMAs, differently in
+// each kernel.
 __device__ __forceinline__ float dist2_nc(float x, float y, float z) {
-  return __fadd_rn(__fadd_rn(__fmul_rn(x, x), __fmul_rn(y, y)), __fmul_rn(z, z));
+#pragma clang fp contract(off)
+  const float xx = x * x, yy = y * y, zz = z * z;
+  return (xx + yy) + zz;
 }
 __device__ __forceinline__ double dist2_nc(double x, double y, double z) {
-  return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
+#pragma clang fp contract(off)
+  const double xx = x * x, yy = y * y, zz = z * z;
+  return (xx + yy) + zz;
 }
 
 // Dense grid cells (more than kSubMin points) carry a sub-grid over a box

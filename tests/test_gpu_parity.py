@@ -213,6 +213,90 @@ def test_knn_f32_lists(kind):
         assert np.all(np.diff(d_got) >= -4e-7 * kth)
 
 
+def _knn_ref_f32(S32, queries, k):
+    """k nearest by (d^2, sorted index), d^2 = (dx dx + dy dy) + dz dz in
+    float32 with every product and sum rounded on its own (numpy float32
+    ufuncs do not fuse)."""
+    out = np.full((len(queries), k), -1, np.int64)
+    for a in range(0, len(queries), 256):
+        q = queries[a:a + 256]
+        D = S32[None, :, :] - S32[q, None, :]
+        d2 = (D[..., 0] * D[..., 0] + D[..., 1] * D[..., 1]) + D[..., 2] * D[..., 2]
+        d2[np.arange(len(q)), q] = np.inf
+        idx = np.argsort(d2, axis=1, kind="stable")[:, :k]
+        out[a:a + 256] = idx
+    return out
+
+
+@pytest.mark.parametrize("kind", ["uniform", "cluster", "filament"])
+@pytest.mark.parametrize("k", [32, 64])
+def test_knn_f32_keys_exact(kind, k):
+    """Float lists are exactly the k smallest (float d^2, sorted index) keys,
+    d^2 rounded term by term: the clip compares its own d^2 with the list's
+    last one bit for bit, so the k-NN must not round it any other way (a
+    fused multiply-add would)."""
+    P = getattr(gen, kind)(20_000, seed=6, dtype=np.float32)
+    pts = torch.from_numpy(P).cuda()
+    cs, perm, srt, grid = vt.grid_sort(pts)
+    S32 = srt[:, :3].cpu().numpy()
+    q = np.sort(np.random.default_rng(1).choice(len(P), 1500, replace=False)).astype(np.int32)
+    got = vt.knn(srt, grid, cs, k, queries=torch.from_numpy(q).cuda(), dist="f32").cpu().numpy()
+    assert np.array_equal(got, _knn_ref_f32(S32, q, k))
+
+
+def _tied_boundary_points(dtype, k=8, n_base=20_000, n_seeds=1500, seed=0):
+    """Uniform points on a dyadic grid; for each chosen seed s, its k-th
+    nearest point q gets a mirror image s + (dy, dx, dz) of q - s = (dx, dy,
+    dz).  The grid makes every coordinate difference exact, so q and its image
+    are at the same distance from s, also when d^2 is rounded term by term
+    (the two sums take the same terms), while a fused multiply-add would
+    round them differently.  Returns the points and the seeds whose k-th and
+    (k+1)-th nearest points are still such a tie."""
+    rng = np.random.default_rng(seed)
+    step = 2.0 ** (-23 if dtype == np.float32 else -50)
+    P = np.round(rng.uniform(0.15, 0.85, (n_base, 3)) / step) * step
+    seeds = rng.choice(n_base, n_seeds, replace=False)
+    add = []
+    for s in seeds:
+        d = ((P - P[s]) ** 2).sum(1)
+        o = np.argpartition(d, k + 1)[:k + 2]
+        o = o[np.argsort(d[o], kind="stable")]
+        off = P[o[k]] - P[s]
+        if abs(off[0] - off[1]) > 1e-3 * np.sqrt(d[o[k]]):  # a distinct point
+            add.append(P[s] + off[[1, 0, 2]])
+    P = np.vstack([P, np.array(add)]).astype(dtype)
+    assert len(np.unique(P, axis=0)) == len(P)
+    X = P.astype(np.float64)
+    tied = []
+    for s in seeds:
+        d = ((X - X[s]) ** 2).sum(1)
+        o = np.argpartition(d, k + 1)[:k + 2]
+        ds = np.sort(d[o])
+        if ds[k] == ds[k + 1]:
+            tied.append(s)
+    return P, np.array(tied)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_ties_at_the_list_boundary(prec):
+    """Lists of 8 whose 8th and 9th points tie exactly: the list keeps the
+    lower sorted index and the stream phase must take the other one (it is a
+    face in most of these cells).  Every cell must match the oracle."""
+    dt = np.float32 if prec == "f32" else np.float64
+    P, tied = _tied_boundary_points(dt)
+    assert len(tied) > 500
+    res = vt.tessellate(torch.from_numpy(P).cuda(), k0=8, max_gpu_retries=0, precision=prec)
+    orc = oracle.tessellate(P.astype(np.float64), volume_ld=True)
+    note(f"  ties {prec}: {len(tied)} seeds with a tie at ranks 8/9; stats {res.stats['passes']}")
+    assert res.stats["fallback_cells"] == 0
+    rp, col = res.row_ptr.cpu().numpy(), res.col.cpu().numpy()
+    for s in tied:
+        assert np.array_equal(col[rp[s]:rp[s + 1]], orc["col"][orc["row_ptr"][s]:orc["row_ptr"][s + 1]]), s
+    assert np.array_equal(rp, orc["row_ptr"]) and np.array_equal(col, orc["col"])
+    viol, rel = volume_errors(res.volume.cpu().numpy(), orc, prec)
+    assert not viol.any(), rel.max()
+
+
 def test_knn_padding_and_small_n():
     P = gen.uniform(5, seed=6, dtype=np.float64)
     pts = torch.from_numpy(P).cuda()
