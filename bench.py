@@ -47,24 +47,36 @@ def knn_bytes_per_query(k: int) -> int:
     return 16 + 4 * k  # read the query's record, write k indices
 
 
+CLIP_SOURCES = ("clip.hip", "device_common.h", "internal.h")
+
+
+def clip_sources_sha256() -> str:
+    """SHA-256 over the clip kernel's sources, in the order of CLIP_SOURCES."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in CLIP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2412_04514_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def clip_traffic(workload: str):
     """HBM bytes per step of all k_clip launches from the committed counter
     summary, only while it was taken on the clip kernel as it stands (the
-    summary records the SHA-256 of clip.hip); None otherwise."""
-    import hashlib
+    summary records the SHA-256 of the sources the kernel is compiled from);
+    None otherwise."""
     prof = os.path.join(ROOT, "profiles", f"clip_traffic_{workload.replace('-', '')}.md")
-    src = os.path.join(ROOT, "paper_2412_04514_amd", "csrc", "clip.hip")
     try:
         text = open(prof).read()
     except OSError:
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = clip_sources_sha256()
     vals = {}
     for ln in text.splitlines():
         if ":" in ln and ln.strip().startswith("- "):
             k, v = ln.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("clip.hip sha256") != sha:
+    if vals.get("clip sources sha256") != sha:
         return None
     try:
         return float(vals["bytes per step"])
