@@ -235,6 +235,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   constexpr unsigned long long LOWL = (L == 64) ? ~0ull : ((1ull << L) - 1);
   constexpr M PFULL = (PMAX == 8 * (int)sizeof(M)) ? ~M(0) : ((M(1) << PMAX) - 1);
   static_assert(S <= 32, "slot mask is 32 bits");
+  static_assert(TMAX <= 256, "vertex slots are numbered in one byte");
 
   __shared__ R vx[G * TP], vy[G * TP], vz[G * TP];
   __shared__ unsigned tri[G * TP];
@@ -242,6 +243,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   __shared__ int pid[G * PMAX];
   __shared__ M omask[G * PMAX];
   __shared__ unsigned snew[G * PMAX];
+  __shared__ unsigned char sslot[G * PMAX];  // free slot taken by new triangle r
   constexpr int TE = RECHECK ? G * TP : 1;
   __shared__ float verr[TE];  // forward error bound of each float vertex
   // stream phase: vertex slots whose ball can reach the current grid row /
@@ -518,9 +520,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       }
     }
     __syncthreads();
-    // new triangles (a, b, ps) into free slots, in slot order
+    // new triangles (a, b, ps) into free slots, in slot order: the slot loop
+    // only assigns the r-th free slot to new triangle r; lane r then solves
+    // its vertex, so that a cut runs the solve once rather than once per slot
+    // index any lane of the wave fills
     int base = 0, hnew = 0;
-    const R mx = nx, my = ny, mz = nz, mc = c;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int t = j + L * s;
@@ -529,31 +533,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       const int r = base + __popc(gbits & ((1u << j) - 1u));
       base += __popc(gbits);
       if (fr && r < btot) {
-        const unsigned e = snew[pb + r];
-        const int A = e & 0xFF, B = (e >> 8) & 0xFF;
-        V3<R> v;
-        if constexpr (RECHECK) {
-          float e;
-          v = solve3_err({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
-                         pnc[pb + B], {mx, my, mz}, mc, e);
-          const float vm = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
-          if (!(e <= 16.0 * a.eps * vm)) {
-            // ill-conditioned float vertex: solve it in double from the exact
-            // planes and keep the rounded value (bound: one ulp)
-            const V3<double> w = vertex64((unsigned)A | ((unsigned)B << 8) | ((unsigned)ps << 16));
-            v = {(float)w.x, (float)w.y, (float)w.z};
-            e = FLT_EPSILON * (float)fmax(fabs(w.x), fmax(fabs(w.y), fabs(w.z)));
-            ++nrecheck;
-          }
-          verr[vb + t] = e;
-        } else {
-          v = solve3<R>({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
-                        pnc[pb + B], {mx, my, mz}, mc);
-        }
-        vx[vb + t] = v.x;
-        vy[vb + t] = v.y;
-        vz[vb + t] = v.z;
-        tri[vb + t] = (unsigned)A | ((unsigned)B << 8) | ((unsigned)ps << 16);
+        sslot[pb + r] = (unsigned char)t;
         hnew = t + 1;
       }
     }
@@ -562,6 +542,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       doit = false;
     }
     hnew = gmaxi(hnew);
+    __syncthreads();
+    const R mx = nx, my = ny, mz = nz, mc = c;
+    for (int r = j; doit && r < btot; r += L) {
+      const int t = sslot[pb + r];
+      const unsigned e = snew[pb + r];
+      const int A = e & 0xFF, B = (e >> 8) & 0xFF;
+      V3<R> v;
+      if constexpr (RECHECK) {
+        float e;
+        v = solve3_err({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
+                       pnc[pb + B], {mx, my, mz}, mc, e);
+        const float vm = fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+        if (!(e <= 16.0 * a.eps * vm)) {
+          // ill-conditioned float vertex: solve it in double from the exact
+          // planes and keep the rounded value (bound: one ulp)
+          const V3<double> w = vertex64((unsigned)A | ((unsigned)B << 8) | ((unsigned)ps << 16));
+          v = {(float)w.x, (float)w.y, (float)w.z};
+          e = FLT_EPSILON * (float)fmax(fabs(w.x), fmax(fabs(w.y), fabs(w.z)));
+          ++nrecheck;
+        }
+        verr[vb + t] = e;
+      } else {
+        v = solve3<R>({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
+                      pnc[pb + B], {mx, my, mz}, mc);
+      }
+      vx[vb + t] = v.x;
+      vy[vb + t] = v.y;
+      vz[vb + t] = v.z;
+      tri[vb + t] = (unsigned)A | ((unsigned)B << 8) | ((unsigned)ps << 16);
+    }
     __syncthreads();
     // rebuild the alive-plane mask and R^2
     if (doit) H = max(H, hnew);
