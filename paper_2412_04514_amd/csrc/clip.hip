@@ -258,6 +258,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   // dense cell is entered, so it need not occupy registers)
   constexpr int FWG = STREAM ? G * 6 : 1;
   __shared__ double fwbox[FWG];
+  // stream phase: point ranges of up to L sub-rows of the dense cell being
+  // scanned (offsets into the cell), per group
+  constexpr int SRL = STREAM ? G * L : 1;
+  __shared__ int2 srl[SRL];
 
   const Rec4* rec = (const Rec4*)a.rec;
   const int lane = threadIdx.x;
@@ -783,7 +787,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     int rx = 1, rx1 = 0, rrow = 0;
     // dense cell rows: z and y outward from the seed's row (0, +1, -1, +2, ...)
     int dm = 0, dm0 = 0, dm1 = 0, dbase = 0, dsx0 = 0, dsx1 = -1, dsy0 = 0, dsy1 = -1, dsz0 = 0, dsz1 = -1;
-    int dq1 = 0, dq2 = 0, ky = 0, kz = 0, kyn = 0, kzn = 0;
+    int dq1 = 0, dq2 = 0, kyn = 0, kzn = 0;
+    int dq = 0, dqn = 0, srn = 0, srp = 0;  // next sub-row ordinal, their count; listed ranges, next one
     const int* dst = nullptr;
     unsigned pend = 0;
     int myj = -1;
@@ -849,22 +854,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     };
     int nR = 0, nD = 0;
     bool okR = false, okD = false;  // lists valid for the current vertices
-    // does a box of candidates meet the ball of a vertex of the dense cell's list?
-    auto dense_box_relevant = [&](double x0, double x1, double y0, double y1, double z0, double z1) -> bool {
-      if (!okD) return true;
-      const double ax = x0 - p64x - gmarg, bx = x1 - p64x + gmarg;
-      const double ay = y0 - p64y - gmarg, by = y1 - p64y + gmarg;
-      const double az = z0 - p64z - gmarg, bz = z1 - p64z + gmarg;
-      bool hit = false;
-      for (int i = j; i < nD && !hit; i += L) {
+    // does sub-row (sy, sz) of the dense cell's sub-block meet the ball of a
+    // vertex of the cell's list?  (one sub-row per lane)
+    auto sub_row_relevant = [&](int sy, int sz) -> bool {
+      const double* dgp = dgeo + g * 9;
+      const int m2 = dst[2];
+      const double X0 = dsx0 == 0 ? dgp[0] : dgp[3] + dsx0 * dgp[6];
+      const double X1 = dsx1 == dm0 - 1 ? dgp[0] + Gd.h0 : dgp[3] + (dsx1 + 1) * dgp[6];
+      const double Y0 = sy == 0 ? dgp[1] : dgp[4] + sy * dgp[7];
+      const double Y1 = sy == dm1 - 1 ? dgp[1] + Gd.h1 : dgp[4] + (sy + 1) * dgp[7];
+      const double Z0 = sz == 0 ? dgp[2] : dgp[5] + sz * dgp[8];
+      const double Z1 = sz == m2 - 1 ? dgp[2] + Gd.h2 : dgp[5] + (sz + 1) * dgp[8];
+      const double ax = X0 - p64x - gmarg, bx = X1 - p64x + gmarg;
+      const double ay = Y0 - p64y - gmarg, by = Y1 - p64y + gmarg;
+      const double az = Z0 - p64z - gmarg, bz = Z1 - p64z + gmarg;
+      for (int i = 0; i < nD; ++i) {
         const int t = relD[g * TMAX + i];
         const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
         const double rv = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-5) + (RECHECK ? 4.0 * (double)verr[vb + t] : 0.0);
         const double gx = fmax(0.0, fmax(ax - X, X - bx)), gy = fmax(0.0, fmax(ay - Y, Y - by)),
                      gz = fmax(0.0, fmax(az - Z, Z - bz));
-        hit = gx * gx + gy * gy + gz * gz <= rv * rv;
+        if (gx * gx + gy * gy + gz * gz <= rv * rv) return true;
       }
-      return group_any(hit);
+      return false;
     };
     bool rdense = false;  // the current range lies in a dense cell
     while (__any(strm && st == ST_RUN)) {
@@ -885,40 +897,66 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
             while (!have_run) {
               if (dm > 0) {
                 // the dense cell's sub-rows inside the flower box, one x-run
-                // each, rows nearer the seed first
-                if (kz >= kzn) {
-                  dm = 0;
+                // each, rows nearer the seed first: the next L of them are
+                // tested and their ranges read at once, one per lane, and the
+                // non-empty ranges listed
+                if (srp >= srn) {
+                  if (dq >= dqn) {
+                    dm = 0;
+                    continue;
+                  }
+                  const int q = dq + j;
+                  dq += L;
+                  bool keep = false;
+                  int lo = 0, hi = 0;
+                  if (q < dqn) {
+                    const int qz = q / kyn, qy = q - qz * kyn;
+                    const int sz = dq2 + ((qz & 1) ? (qz + 1) >> 1 : -(qz >> 1));
+                    const int sy = dq1 + ((qy & 1) ? (qy + 1) >> 1 : -(qy >> 1));
+                    if (sz >= dsz0 && sz <= dsz1 && sy >= dsy0 && sy <= dsy1 && (!okD || sub_row_relevant(sy, sz))) {
+                      const int rowb = kSubHead + dm0 * (sy + dm1 * sz);
+                      lo = dst[rowb + dsx0];
+                      hi = dst[rowb + dsx1 + 1];
+                      keep = lo < hi;
+                    }
+                  }
+                  int tot;
+                  const int w = gexcl(keep ? 1 : 0, tot);
+                  if (keep) srl[g * L + w] = make_int2(lo, hi);
+                  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                  srn = tot;
+                  srp = 0;
                   continue;
                 }
-                const int sz = dq2 + ((kz & 1) ? (kz + 1) >> 1 : -(kz >> 1));
-                const int sy = dq1 + ((ky & 1) ? (ky + 1) >> 1 : -(ky >> 1));
-                if (++ky >= kyn) { ky = 0; ++kz; }
-                if (sz < dsz0 || sz > dsz1 || sy < dsy0 || sy > dsy1) continue;
-                const int sx0 = dsx0, sx1 = dsx1;
-                if (okD) {
-                  // skip the sub-row when no listed vertex ball reaches it
-                  const double* dgp = dgeo + g * 9;
-                  const int m2 = dst[2];
-                  const double X0 = sx0 == 0 ? dgp[0] : dgp[3] + sx0 * dgp[6];
-                  const double X1 = sx1 == dm0 - 1 ? dgp[0] + Gd.h0 : dgp[3] + (sx1 + 1) * dgp[6];
-                  const double Y0 = sy == 0 ? dgp[1] : dgp[4] + sy * dgp[7];
-                  const double Y1 = sy == dm1 - 1 ? dgp[1] + Gd.h1 : dgp[4] + (sy + 1) * dgp[7];
-                  const double Z0 = sz == 0 ? dgp[2] : dgp[5] + sz * dgp[8];
-                  const double Z1 = sz == m2 - 1 ? dgp[2] + Gd.h2 : dgp[5] + (sz + 1) * dgp[8];
-                  if (!dense_box_relevant(X0, X1, Y0, Y1, Z0, Z1)) continue;
-                }
-                const int rowb = kSubHead + dm0 * (sy + dm1 * sz);
-                jcur = dbase + dst[rowb + sx0];
-                jend = dbase + dst[rowb + sx1 + 1];
-                have_run = jcur < jend;
+                const int2 rg = srl[g * L + srp];
+                ++srp;
+                jcur = dbase + rg.x;
+                jend = dbase + rg.y;
+                have_run = true;
                 rdense = true;
                 continue;
               }
               if (rx <= rx1) {
                 int xe = rx1 + 1;
                 if (a.sub.info) {
+                  // the stretch of cells without sub-grids: the group reads L
+                  // consecutive cells' records at once and ends it at the
+                  // first dense one
                   xe = rx;
-                  while (xe <= rx1 && a.sub.info[rrow + xe].x < 0) ++xe;
+                  for (;;) {
+                    const int xc = xe + j;
+                    const bool dn = xc <= rx1 && a.sub.info[rrow + xc].x >= 0;
+                    const unsigned long long dmask = (__ballot(dn) >> gb) & LOWL;
+                    if (dmask) {
+                      xe += __ffsll((long long)dmask) - 1;
+                      break;
+                    }
+                    xe += L;
+                    if (xe > rx1) {
+                      xe = rx1 + 1;
+                      break;
+                    }
+                  }
                 }
                 if (xe > rx) {
                   jcur = a.cell_start[rrow + rx];
@@ -971,7 +1009,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
                 // offsets 0, +1, -1, ... up to the farther end of each range
                 kyn = 2 * max(dq1 - dsy0, dsy1 - dq1) + 1;
                 kzn = 2 * max(dq2 - dsz0, dsz1 - dq2) + 1;
-                ky = kz = 0;
+                dq = 0;
+                dqn = kyn * kzn;
+                srn = srp = 0;
                 ++rx;
                 continue;
               }
@@ -1020,11 +1060,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
             }
             if (done) break;
           }
-          // batch of L candidates, one per lane, filtered by list key and radius
-          const int jj = jcur + j;
+          // batch of up to L candidates, one per lane: the rest of the current
+          // range, then (in a dense cell) the following listed sub-rows;
+          // filtered by list key and radius
+          int jj = -1;
+          {
+            int nb = 0;
+            for (;;) {
+              const int take = min(L - nb, jend - jcur);
+              if (j >= nb && j < nb + take) jj = jcur + (j - nb);
+              nb += take;
+              jcur += take;
+              if (nb == L || !rdense || srp >= srn) break;
+              const int2 rg = srl[g * L + srp];
+              ++srp;
+              jcur = dbase + rg.x;
+              jend = dbase + rg.y;
+            }
+          }
           bool pass = false;
           myj = -1;
-          if (jj < jend && jj != sid) {
+          if (jj >= 0 && jj != sid) {
             const Rec4 q = rec[jj];
             const R d2c = dist2_nc((R)q.x - px, (R)q.y - py, (R)q.z - pz);
             const bool beyond_list = d2c > dk2 || (d2c == dk2 && jj > ik);
@@ -1063,7 +1119,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
             myj = jj;
             myd2 = d2c;
           }
-          jcur += L;
           pend = (unsigned)((__ballot(pass) >> gb) & LOWL);
           if (!pass) myj = -1;
           if (pend) break;
