@@ -246,6 +246,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   __shared__ unsigned char sslot[G * PMAX];  // free slot taken by new triangle r
   constexpr int TE = RECHECK ? G * TP : 1;
   __shared__ float verr[TE];  // forward error bound of each float vertex
+  // stream phase of the float clip: radius of each vertex's ball through the
+  // seed, widened past the vertex's error bound and the rounding of the tests
+  // that use it (the double clip recomputes it where needed: measured faster)
+  constexpr bool kVrad = STREAM && RECHECK;
+  constexpr int VRD = kVrad ? G * TP : 1;
+  __shared__ float vrad[VRD];
   // stream phase: vertex slots whose ball can reach the current grid row /
   // dense cell (see below)
   constexpr int RL = STREAM ? G * TMAX : 1;
@@ -376,6 +382,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     return !rad_certain(dd2) && (double)dd2 * a.dmargin * (1.0 + a.eps) > 4.0 * (double)R2lo;
   };
   bool fmarg = false;  // the last F test was inside its recheck window
+  bool in_stream = false;  // the group's cell is in the stream phase (vrad kept)
+  // |v| (1 + 1e-5) + 4 verr.  verr bounds each coordinate of the float
+  // vertex, so the true ball's centre lies within verr per axis and its radius
+  // within sqrt(3) verr: 4 verr > (1 + sqrt(3)) verr covers both; the relative
+  // 1e-5 covers the rounding of this radius and of the box-ball tests, made in
+  // the clip's precision.
+  auto ball_rad = [&](R X, R Y, R Z, float e) -> R {
+    if constexpr (sizeof(R) == 4) {
+      return sqrtf(X * X + Y * Y + Z * Z) * (1.0f + 1e-5f) + 4.0f * e;
+    } else {
+      return sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-5);
+    }
+  };
+  // the ball radius of vertex slot t (at X, Y, Z)
+  auto vball = [&](int t, R X, R Y, R Z) -> R {
+    if constexpr (kVrad) {
+      return vrad[vb + t];
+    } else {
+      return ball_rad(X, Y, Z, RECHECK ? verr[vb + t] : 0.0f);
+    }
+  };
   bool fprev = false;
   int kneed = 0;
   int nrecheck = 0;
@@ -553,6 +580,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       const unsigned e = snew[pb + r];
       const int A = e & 0xFF, B = (e >> 8) & 0xFF;
       V3<R> v;
+      float ev = 0.0f;
       if constexpr (RECHECK) {
         float e;
         v = solve3_err({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
@@ -567,6 +595,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
           ++nrecheck;
         }
         verr[vb + t] = e;
+        ev = e;
       } else {
         v = solve3<R>({pnx[pb + A], pny[pb + A], pnz[pb + A]}, pnc[pb + A], {pnx[pb + B], pny[pb + B], pnz[pb + B]},
                       pnc[pb + B], {mx, my, mz}, mc);
@@ -574,6 +603,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       vx[vb + t] = v.x;
       vy[vb + t] = v.y;
       vz[vb + t] = v.z;
+      if constexpr (kVrad) {
+        if (in_stream) vrad[vb + t] = ball_rad(v.x, v.y, v.z, ev);
+      }
       tri[vb + t] = (unsigned)A | ((unsigned)B << 8) | ((unsigned)ps << 16);
     }
     __syncthreads();
@@ -730,6 +762,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     const int ik0 = (have && st == VOTESS_CELL_RADIUS && !nolist) ? a.knn[(size_t)t_idx * a.k + a.k - 1] : -1;
     const bool strm = have && st == VOTESS_CELL_RADIUS && (nolist || ik0 >= 0);  // a full list that did not certify
     if (strm) st = ST_RUN;
+    if constexpr (kVrad) {
+      // ball radii of the current vertices (kept up to date from here on)
+      in_stream = strm;
+      for (int t = j; t < H; t += L)
+        if (strm && tri[vb + t] != kEmpty) vrad[vb + t] = ball_rad(vx[vb + t], vy[vb + t], vz[vb + t], verr[vb + t]);
+      __syncthreads();
+    }
     if (strm && j == 0 && a.counters) atomicAdd(&a.counters[5], 1ull);
     const GridDev& Gd = a.grid;
     const int cx = axis_cell(p64x, Gd.lo0, Gd.ih0, Gd.g0);
@@ -751,11 +790,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       for (int t = j; t < H; t += L) {
         if (tri[vb + t] == kEmpty) continue;
         const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
-        // verr bounds each coordinate of the float vertex, so the true ball's
-        // centre lies within verr per axis (a box of half-width verr) and its
-        // radius within sqrt(3) verr: widening by 4 verr > (1 + sqrt(3)) verr
-        // covers both
-        const double rad = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-6) + (RECHECK ? 4.0 * (double)verr[vb + t] : 0.0);
+        const double rad = vball(t, vx[vb + t], vy[vb + t], vz[vb + t]);
         mn0 = fmin(mn0, X - rad); mx0 = fmax(mx0, X + rad);
         mn1 = fmin(mn1, Y - rad); mx1 = fmax(mx1, Y + rad);
         mn2 = fmin(mn2, Z - rad); mx2 = fmax(mx2, Z + rad);
@@ -827,20 +862,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     // listed in `out`; none: the box cannot hold a cutting point.  The balls
     // are widened past rounding and the float path's vertex error bounds.
     // Lists name vertex slots, so a cut (which reuses slots) invalidates them.
+    // Box bounds enter the tests in the clip's precision rounded outward, so
+    // that the box only grows.
+    auto out_lo = [](double v) -> R {
+      if constexpr (sizeof(R) == 4) {
+        const float f = (float)v;
+        return (double)f > v ? nextafterf(f, -INFINITY) : f;
+      } else {
+        return v;
+      }
+    };
+    auto out_hi = [](double v) -> R {
+      if constexpr (sizeof(R) == 4) {
+        const float f = (float)v;
+        return (double)f < v ? nextafterf(f, INFINITY) : f;
+      } else {
+        return v;
+      }
+    };
     auto relevant = [&](unsigned char* out, double x0, double x1, double y0, double y1, double z0,
                         double z1) -> int {
-      const double ax = x0 - p64x - gmarg, bx = x1 - p64x + gmarg;
-      const double ay = y0 - p64y - gmarg, by = y1 - p64y + gmarg;
-      const double az = z0 - p64z - gmarg, bz = z1 - p64z + gmarg;
+      const R ax = out_lo(x0 - p64x - gmarg), bx = out_hi(x1 - p64x + gmarg);
+      const R ay = out_lo(y0 - p64y - gmarg), by = out_hi(y1 - p64y + gmarg);
+      const R az = out_lo(z0 - p64z - gmarg), bz = out_hi(z1 - p64z + gmarg);
       unsigned bits = 0;
 #pragma unroll
       for (int s2 = 0; s2 < S; ++s2) {
         const int t = j + L * s2;
         if (t < H && tri[vb + t] != kEmpty) {
-          const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
-          const double rv = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-5) + (RECHECK ? 4.0 * (double)verr[vb + t] : 0.0);
-          const double gx = fmax(0.0, fmax(ax - X, X - bx)), gy = fmax(0.0, fmax(ay - Y, Y - by)),
-                       gz = fmax(0.0, fmax(az - Z, Z - bz));
+          const R X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+          const R rv = vball(t, X, Y, Z);
+          const R gx = fmax(R(0), fmax(ax - X, X - bx)), gy = fmax(R(0), fmax(ay - Y, Y - by)),
+                  gz = fmax(R(0), fmax(az - Z, Z - bz));
           if (gx * gx + gy * gy + gz * gz <= rv * rv) bits |= 1u << s2;
         }
       }
@@ -865,15 +918,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       const double Y1 = sy == dm1 - 1 ? dgp[1] + Gd.h1 : dgp[4] + (sy + 1) * dgp[7];
       const double Z0 = sz == 0 ? dgp[2] : dgp[5] + sz * dgp[8];
       const double Z1 = sz == m2 - 1 ? dgp[2] + Gd.h2 : dgp[5] + (sz + 1) * dgp[8];
-      const double ax = X0 - p64x - gmarg, bx = X1 - p64x + gmarg;
-      const double ay = Y0 - p64y - gmarg, by = Y1 - p64y + gmarg;
-      const double az = Z0 - p64z - gmarg, bz = Z1 - p64z + gmarg;
+      const R ax = out_lo(X0 - p64x - gmarg), bx = out_hi(X1 - p64x + gmarg);
+      const R ay = out_lo(Y0 - p64y - gmarg), by = out_hi(Y1 - p64y + gmarg);
+      const R az = out_lo(Z0 - p64z - gmarg), bz = out_hi(Z1 - p64z + gmarg);
       for (int i = 0; i < nD; ++i) {
         const int t = relD[g * TMAX + i];
-        const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
-        const double rv = sqrt(X * X + Y * Y + Z * Z) * (1.0 + 1e-5) + (RECHECK ? 4.0 * (double)verr[vb + t] : 0.0);
-        const double gx = fmax(0.0, fmax(ax - X, X - bx)), gy = fmax(0.0, fmax(ay - Y, Y - by)),
-                     gz = fmax(0.0, fmax(az - Z, Z - bz));
+        const R X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
+        const R rv = vball(t, X, Y, Z);
+        const R gx = fmax(R(0), fmax(ax - X, X - bx)), gy = fmax(R(0), fmax(ay - Y, Y - by)),
+                gz = fmax(R(0), fmax(az - Z, Z - bz));
         if (gx * gx + gy * gy + gz * gz <= rv * rv) return true;
       }
       return false;
