@@ -268,6 +268,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   // scanned (offsets into the cell), per group
   constexpr int SRL = STREAM ? G * L : 1;
   __shared__ int2 srl[SRL];
+  // stream phase: the group's enumeration state (grid ring, x-run, dense
+  // sub-block, flower box in cells).  Every value is the same for all lanes
+  // of a group; held here rather than in registers, which the rest of the
+  // kernel needs.
+  struct Enum {
+    int fb0, fb1, fb2, fb3, fb4, fb5;
+    int rr, zz, yy, part, zhi, ylo, yhi;
+    int rx, rx1, rrow;
+    int dm, dm0, dm1, dbase, dsx0, dsx1, dsy0, dsy1, dsz0, dsz1, dsto;
+    int dq1, dq2, kyn, kzn, dq, dqn, srn, srp;
+  };
+  __shared__ Enum senum[STREAM ? G : 1];
 
   const Rec4* rec = (const Rec4*)a.rec;
   const int lane = threadIdx.x;
@@ -783,7 +795,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       dk2 = dist2_nc((R)q.x - px, (R)q.y - py, (R)q.z - pz);
     }
     // flower box in grid cells, from the current vertices (group reduction)
-    int fb0 = 0, fb1 = -1, fb2 = 0, fb3 = -1, fb4 = 0, fb5 = -1;
+    Enum& E_ = senum[STREAM ? g : 0];
+    int &fb0 = E_.fb0, &fb1 = E_.fb1, &fb2 = E_.fb2, &fb3 = E_.fb3, &fb4 = E_.fb4, &fb5 = E_.fb5;
+    fb0 = 0; fb1 = -1; fb2 = 0; fb3 = -1; fb4 = 0; fb5 = -1;
     double* fwb = fwbox + (STREAM ? g * 6 : 0);  // the same box in coordinates
     auto flower_box = [&]() {
       double mn0 = 1e300, mn1 = 1e300, mn2 = 1e300, mx0 = -1e300, mx1 = -1e300, mx2 = -1e300;
@@ -815,16 +829,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       fb4 = axis_cell(fw4, Gd.lo2, Gd.ih2, Gd.g2);
       fb5 = axis_cell(fw5, Gd.lo2, Gd.ih2, Gd.g2);
     };
-    int rr = -1, zz = 0, yy = 0, part = 0, zhi = -1, ylo = 0, yhi = -1;
+    int &rr = E_.rr, &zz = E_.zz, &yy = E_.yy, &part = E_.part, &zhi = E_.zhi, &ylo = E_.ylo, &yhi = E_.yhi;
+    rr = -1; zz = 0; yy = 0; part = 0; zhi = -1; ylo = 0; yhi = -1;
     int jcur = 0, jend = 0;
     // the x-run being split at dense cells, and the sub-block of the dense
     // cell being scanned (sub-cells that meet the flower box)
-    int rx = 1, rx1 = 0, rrow = 0;
+    int &rx = E_.rx, &rx1 = E_.rx1, &rrow = E_.rrow;
+    rx = 1; rx1 = 0; rrow = 0;
     // dense cell rows: z and y outward from the seed's row (0, +1, -1, +2, ...)
-    int dm = 0, dm0 = 0, dm1 = 0, dbase = 0, dsx0 = 0, dsx1 = -1, dsy0 = 0, dsy1 = -1, dsz0 = 0, dsz1 = -1;
-    int dq1 = 0, dq2 = 0, kyn = 0, kzn = 0;
-    int dq = 0, dqn = 0, srn = 0, srp = 0;  // next sub-row ordinal, their count; listed ranges, next one
-    const int* dst = nullptr;
+    int &dm = E_.dm, &dm0 = E_.dm0, &dm1 = E_.dm1, &dbase = E_.dbase, &dsx0 = E_.dsx0, &dsx1 = E_.dsx1,
+        &dsy0 = E_.dsy0, &dsy1 = E_.dsy1, &dsz0 = E_.dsz0, &dsz1 = E_.dsz1;
+    dm = 0; dm0 = 0; dm1 = 0; dbase = 0; dsx0 = 0; dsx1 = -1; dsy0 = 0; dsy1 = -1; dsz0 = 0; dsz1 = -1;
+    int &dq1 = E_.dq1, &dq2 = E_.dq2, &kyn = E_.kyn, &kzn = E_.kzn;
+    dq1 = 0; dq2 = 0; kyn = 0; kzn = 0;
+    // next sub-row ordinal, their count; listed ranges, next one
+    int &dq = E_.dq, &dqn = E_.dqn, &srn = E_.srn, &srp = E_.srp;
+    dq = 0; dqn = 0; srn = 0; srp = 0;
+    int& dsto = E_.dsto;  // the dense cell's sub-grid record: a.sub.start + dsto
+    dsto = 0;
     unsigned pend = 0;
     int myj = -1;
     R myd2 = R(0);
@@ -911,7 +933,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     // vertex of the cell's list?  (one sub-row per lane)
     auto sub_row_relevant = [&](int sy, int sz) -> bool {
       const double* dgp = dgeo + g * 9;
-      const int m2 = dst[2];
+      const int m2 = a.sub.start[dsto + 2];
       const double X0 = dsx0 == 0 ? dgp[0] : dgp[3] + dsx0 * dgp[6];
       const double X1 = dsx1 == dm0 - 1 ? dgp[0] + Gd.h0 : dgp[3] + (dsx1 + 1) * dgp[6];
       const double Y0 = sy == 0 ? dgp[1] : dgp[4] + sy * dgp[7];
@@ -968,8 +990,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
                     const int sy = dq1 + ((qy & 1) ? (qy + 1) >> 1 : -(qy >> 1));
                     if (sz >= dsz0 && sz <= dsz1 && sy >= dsy0 && sy <= dsy1 && (!okD || sub_row_relevant(sy, sz))) {
                       const int rowb = kSubHead + dm0 * (sy + dm1 * sz);
-                      lo = dst[rowb + dsx0];
-                      hi = dst[rowb + dsx1 + 1];
+                      lo = a.sub.start[dsto + rowb + dsx0];
+                      hi = a.sub.start[dsto + rowb + dsx1 + 1];
                       keep = lo < hi;
                     }
                   }
@@ -1052,7 +1074,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
                     continue;
                   }
                 }
-                dst = a.sub.start + info.x;
+                dsto = info.x;
                 dbase = a.cell_start[rrow + rx];
                 dm = 1;
                 dm0 = sc.m0;
