@@ -166,6 +166,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   constexpr int FB = kSortFill ? (256 / GS) * K : 1;
   __shared__ Key sfill[FB];
   Key* gfill = sfill + (kSortFill ? ((threadIdx.x & 255) / GS) * K : 0);
+  // phase B: point ranges of up to GS sub-rows of a dense cell (two per
+  // sub-row at most), per group
+  __shared__ int2 srng[(256 / GS) * 2 * GS];
+  int2* grng = srng + ((threadIdx.x & 255) / GS) * 2 * GS;
   bool filling = kSortFill;
   int nfill = 0;
   const double p0 = (double)pr.x, p1 = (double)pr.y, p2 = (double)pr.z;
@@ -202,6 +206,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       } else {
         pass = O::less(ck, wk);
       }
+      unsigned long long m = (__ballot(pass) >> gb) & gmask;
+      while (m) {
+        const int b = __ffsll((long long)m) - 1;
+        const Key x = O::shfl(ck, gb + b);
+        L.insert(x, lane, l);
+        wk = L.worst(gb);
+        pass = pass && l != b && O::less(ck, wk);
+        m = (__ballot(pass) >> gb) & gmask;
+      }
+    }
+  };
+  // candidates of the n ranges listed in grng, GS at a time, a batch taking
+  // the rest of one range and the start of the next ones (the list is full
+  // here: no initial fill)
+  auto scan_list = [&](int n) {
+    int r = 0;
+    int cur = 0, end = 0;
+    if (n > 0) {
+      cur = grng[0].x;
+      end = grng[0].y;
+    }
+    while (r < n) {
+      int jj = -1, nb = 0;
+      while (nb < GS && r < n) {
+        const int take = min(GS - nb, end - cur);
+        if (l >= nb && l < nb + take) jj = cur + (l - nb);
+        nb += take;
+        cur += take;
+        if (cur >= end && ++r < n) {
+          cur = grng[r].x;
+          end = grng[r].y;
+        }
+      }
+      Key ck = O::inf();
+      if (jj >= 0 && jj != s) {
+        const auto qr = rec[jj];
+        ck = O::make(dist2_nc((D)qr.x - px, (D)qr.y - py, (D)qr.z - pz), jj);
+      }
+      bool pass = O::less(ck, wk);
       unsigned long long m = (__ballot(pass) >> gb) & gmask;
       while (m) {
         const int b = __ffsll((long long)m) - 1;
@@ -292,30 +335,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int base = cell_start[c];
     const double w1 = 1.0 / sc.ih1, w2 = 1.0 / sc.ih2;
     const double ylo = G.lo1 + ccy * G.h1, yhi = ylo + G.h1, zlo = G.lo2 + ccz * G.h2, zhi = zlo + G.h2;
-    const double rz = sqrt(rad2()) + margin;
-    const int sz0 = sub_axis(p2 - rz, sc.lo2, sc.ih2, sc.m2), sz1 = sub_axis(p2 + rz, sc.lo2, sc.ih2, sc.m2);
-    for (int sz = sz0; sz <= sz1; ++sz) {
-      // edge sub-cells reach the cell's faces (points beyond the sub-grid box)
-      const double za = sz == 0 ? zlo : sc.lo2 + sz * w2, zb = sz == sc.m2 - 1 ? zhi : sc.lo2 + (sz + 1) * w2;
-      const double gz = gap(p2, za, zb);
-      const double remz = rad2() - gz * gz;
-      if (remz < 0.0) continue;
-      const double ry = sqrt(remz) + margin;
-      const int sy0 = sub_axis(p1 - ry, sc.lo1, sc.ih1, sc.m1), sy1 = sub_axis(p1 + ry, sc.lo1, sc.ih1, sc.m1);
-      for (int sy = sy0; sy <= sy1; ++sy) {
+    // sub-rows (sy, sz) of the square that meets the ball, GS at a time, one
+    // per lane: each lane cuts its sub-row to the ball and reads its point
+    // range(s); the non-empty ranges are listed and scanned together
+    const double r0 = sqrt(rad2()) + margin;
+    const int sz0 = sub_axis(p2 - r0, sc.lo2, sc.ih2, sc.m2), sz1 = sub_axis(p2 + r0, sc.lo2, sc.ih2, sc.m2);
+    const int sy0 = sub_axis(p1 - r0, sc.lo1, sc.ih1, sc.m1), sy1 = sub_axis(p1 + r0, sc.lo1, sc.ih1, sc.m1);
+    const int ny = sy1 - sy0 + 1, npairs = ny * (sz1 - sz0 + 1);
+    for (int pb = 0; pb < npairs; pb += GS) {
+      const int pi = pb + l;
+      int lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+      if (pi < npairs) {
+        const int sz = sz0 + pi / ny, sy = sy0 + pi % ny;
+        const double za = sz == 0 ? zlo : sc.lo2 + sz * w2, zb = sz == sc.m2 - 1 ? zhi : sc.lo2 + (sz + 1) * w2;
         const double ya = sy == 0 ? ylo : sc.lo1 + sy * w1, yb = sy == sc.m1 - 1 ? yhi : sc.lo1 + (sy + 1) * w1;
-        const double gy = gap(p1, ya, yb);
+        const double gz = gap(p2, za, zb), gy = gap(p1, ya, yb);
         const double rem = rad2() - gz * gz - gy * gy;
-        if (rem < 0.0) continue;
-        const double rx = sqrt(rem) + margin;
-        int sx0 = sub_axis(p0 - rx, sc.lo0, sc.ih0, sc.m0), sx1 = sub_axis(p0 + rx, sc.lo0, sc.ih0, sc.m0);
-        const int row = kSubHead + sc.m0 * (sy + sc.m1 * sz);
-        if (own && sy >= by0 && sy <= by1 && sz >= bz0 && sz <= bz1) {
-          if (sx0 < bx0) scan(base + drec[row + sx0], base + drec[row + min(sx1, bx0 - 1) + 1]);
-          sx0 = max(sx0, bx1 + 1);
+        if (rem >= 0.0) {
+          const double rx = sqrt(rem) + margin;
+          int sx0 = sub_axis(p0 - rx, sc.lo0, sc.ih0, sc.m0), sx1 = sub_axis(p0 + rx, sc.lo0, sc.ih0, sc.m0);
+          const int row = kSubHead + sc.m0 * (sy + sc.m1 * sz);
+          if (own && sy >= by0 && sy <= by1 && sz >= bz0 && sz <= bz1) {
+            // the seed block's sub-cells were scanned whole
+            if (sx0 < bx0) {
+              lo0 = base + drec[row + sx0];
+              hi0 = base + drec[row + min(sx1, bx0 - 1) + 1];
+            }
+            sx0 = max(sx0, bx1 + 1);
+          }
+          if (sx0 <= sx1) {
+            lo1 = base + drec[row + sx0];
+            hi1 = base + drec[row + sx1 + 1];
+          }
         }
-        if (sx0 <= sx1) scan(base + drec[row + sx0], base + drec[row + sx1 + 1]);
       }
+      const bool k0 = lo0 < hi0, k1 = lo1 < hi1;
+      const unsigned long long b0 = (__ballot(k0) >> gb) & gmask, b1 = (__ballot(k1) >> gb) & gmask;
+      const unsigned long long below = (1ull << l) - 1ull;
+      const int w = __popcll(b0 & below) + __popcll(b1 & below);
+      if (k0) grng[w] = make_int2(lo0, hi0);
+      if (k1) grng[w + (k0 ? 1 : 0)] = make_int2(lo1, hi1);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      scan_list(__popcll(b0) + __popcll(b1));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
   };
   if (O::finite(wk)) {
