@@ -175,6 +175,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
   const double p0 = (double)pr.x, p1 = (double)pr.y, p2 = (double)pr.z;
   const unsigned long long gmask = (GS == 64) ? ~0ull : ((1ull << GS) - 1ull);
 
+  // one candidate per lane (ck: its key, infinite when !valid): gathered
+  // into the initial fill while that lasts, else inserted when it beats the
+  // k-th
+  auto consider = [&](bool valid, Key ck) {
+    bool pass;
+    if (kSortFill && filling) {
+      const unsigned long long vm = (__ballot(valid) >> gb) & gmask;
+      const int pos = nfill + __popcll(vm & ((1ull << l) - 1ull));
+      if (valid && pos < K) gfill[pos] = ck;
+      nfill += __popcll(vm);
+      if (nfill < K) return;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+      for (int e = 0; e < E; ++e) L.key[e] = gfill[l * E + e];
+      L.sort(l);
+      wk = L.worst(gb);
+      filling = false;
+      pass = valid && pos >= K && O::less(ck, wk);  // the batch's candidates past the first K
+    } else {
+      pass = O::less(ck, wk);
+    }
+    unsigned long long m = (__ballot(pass) >> gb) & gmask;
+    while (m) {
+      const int b = __ffsll((long long)m) - 1;
+      const Key x = O::shfl(ck, gb + b);
+      L.insert(x, lane, l);
+      wk = L.worst(gb);
+      pass = pass && l != b && O::less(ck, wk);
+      m = (__ballot(pass) >> gb) & gmask;
+    }
+  };
   // candidates [jb, je), GS at a time; each that beats the k-th is inserted
   // with float keys the records of a batch are loaded one batch ahead, so
   // that their latency overlaps the previous batch's ranking and insertions
@@ -189,37 +220,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       Key ck = O::inf();
       const bool valid = j < je && j != s;
       if (valid) ck = O::make(dist2_nc((D)qr.x - px, (D)qr.y - py, (D)qr.z - pz), j);
-      bool pass;
-      if (kSortFill && filling) {
-        const unsigned long long vm = (__ballot(valid) >> gb) & gmask;
-        const int pos = nfill + __popcll(vm & ((1ull << l) - 1ull));
-        if (valid && pos < K) gfill[pos] = ck;
-        nfill += __popcll(vm);
-        if (nfill < K) continue;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-        for (int e = 0; e < E; ++e) L.key[e] = gfill[l * E + e];
-        L.sort(l);
-        wk = L.worst(gb);
-        filling = false;
-        pass = valid && pos >= K && O::less(ck, wk);  // the batch's candidates past the first K
-      } else {
-        pass = O::less(ck, wk);
-      }
-      unsigned long long m = (__ballot(pass) >> gb) & gmask;
-      while (m) {
-        const int b = __ffsll((long long)m) - 1;
-        const Key x = O::shfl(ck, gb + b);
-        L.insert(x, lane, l);
-        wk = L.worst(gb);
-        pass = pass && l != b && O::less(ck, wk);
-        m = (__ballot(pass) >> gb) & gmask;
-      }
+      consider(valid, ck);
     }
   };
   // candidates of the n ranges listed in grng, GS at a time, a batch taking
-  // the rest of one range and the start of the next ones (the list is full
-  // here: no initial fill)
+  // the rest of one range and the start of the next ones
   auto scan_list = [&](int n) {
     int r = 0;
     int cur = 0, end = 0;
@@ -240,21 +245,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         }
       }
       Key ck = O::inf();
-      if (jj >= 0 && jj != s) {
+      const bool valid = jj >= 0 && jj != s;
+      if (valid) {
         const auto qr = rec[jj];
         ck = O::make(dist2_nc((D)qr.x - px, (D)qr.y - py, (D)qr.z - pz), jj);
       }
-      bool pass = O::less(ck, wk);
-      unsigned long long m = (__ballot(pass) >> gb) & gmask;
-      while (m) {
-        const int b = __ffsll((long long)m) - 1;
-        const Key x = O::shfl(ck, gb + b);
-        L.insert(x, lane, l);
-        wk = L.worst(gb);
-        pass = pass && l != b && O::less(ck, wk);
-        m = (__ballot(pass) >> gb) & gmask;
-      }
+      consider(valid, ck);
     }
+  };
+  // scans the rows (y, z) of a block [y0, y1] x [z0, z1]: row_range(y, z)
+  // gives a row's point range; GS rows at a time, one per lane, listed and
+  // scanned together
+  auto scan_rows = [&](int y0, int y1, int z0, int z1, auto row_range) {
+    const int ny = y1 - y0 + 1, npairs = ny * (z1 - z0 + 1);
+    for (int pb = 0; pb < npairs; pb += GS) {
+      const int pi = pb + l;
+      int2 rg = make_int2(0, 0);
+      if (pi < npairs) rg = row_range(y0 + pi % ny, z0 + pi / ny);
+      const bool k0 = rg.x < rg.y;
+      const unsigned long long b0 = (__ballot(k0) >> gb) & gmask;
+      if (k0) grng[__popcll(b0 & ((1ull << l) - 1ull))] = rg;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      scan_list(__popcll(b0));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+  };
+  // number of points in the rows of a block, summed over the group's lanes
+  auto count_rows = [&](int y0, int y1, int z0, int z1, auto row_range) -> int {
+    const int ny = y1 - y0 + 1, npairs = ny * (z1 - z0 + 1);
+    int cnt = 0;
+    for (int pi = l; pi < npairs; pi += GS) {
+      const int2 rg = row_range(y0 + pi % ny, z0 + pi / ny);
+      cnt += rg.y - rg.x;
+    }
+#pragma unroll
+    for (int o = 1; o < GS; o <<= 1) cnt += __shfl_xor(cnt, o, 64);
+    return cnt;
   };
   // squared search radius: the k-th distance with slack for float rounding
   // of d^2 (the list is full whenever it is used)
@@ -275,45 +301,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int base0 = cell_start[c0];
     const int qx = sub_axis(p0, sc.lo0, sc.ih0, sc.m0), qy = sub_axis(p1, sc.lo1, sc.ih1, sc.m1),
               qz = sub_axis(p2, sc.lo2, sc.ih2, sc.m2);
+    auto srow = [&](int y, int z) {
+      const int row = kSubHead + sc.m0 * (y + sc.m1 * z);
+      return make_int2(base0 + srec[row + bx0], base0 + srec[row + bx1 + 1]);
+    };
     for (int rs = 0;; ++rs) {
       bx0 = max(qx - rs, 0); bx1 = min(qx + rs, sc.m0 - 1);
       by0 = max(qy - rs, 0); by1 = min(qy + rs, sc.m1 - 1);
       bz0 = max(qz - rs, 0); bz1 = min(qz + rs, sc.m2 - 1);
-      int cnt = 0;
-      for (int z = bz0; z <= bz1; ++z)
-        for (int y = by0; y <= by1; ++y) {
-          const int row = kSubHead + sc.m0 * (y + sc.m1 * z);
-          cnt += srec[row + bx1 + 1] - srec[row + bx0];
-        }
+      const int cnt = count_rows(by0, by1, bz0, bz1, srow);
       if (cnt >= K + 1 || (bx0 == 0 && by0 == 0 && bz0 == 0 && bx1 == sc.m0 - 1 && by1 == sc.m1 - 1 &&
                            bz1 == sc.m2 - 1))
         break;
     }
-    for (int z = bz0; z <= bz1; ++z)
-      for (int y = by0; y <= by1; ++y) {
-        const int row = kSubHead + sc.m0 * (y + sc.m1 * z);
-        scan(base0 + srec[row + bx0], base0 + srec[row + bx1 + 1]);
-      }
+    scan_rows(by0, by1, bz0, bz1, srow);
   } else {
+    auto grow = [&](int y, int z) {
+      const int row = G.g0 * (y + G.g1 * z);
+      return make_int2(cell_start[row + bx0], cell_start[row + bx1 + 1]);
+    };
     for (int r = 0;; ++r) {
       bx0 = max(cx - r, 0); bx1 = min(cx + r, G.g0 - 1);
       by0 = max(cy - r, 0); by1 = min(cy + r, G.g1 - 1);
       bz0 = max(cz - r, 0); bz1 = min(cz + r, G.g2 - 1);
-      int cnt = 0;
-      for (int z = bz0; z <= bz1; ++z)
-        for (int y = by0; y <= by1; ++y) {
-          const int row = G.g0 * (y + G.g1 * z);
-          cnt += cell_start[row + bx1 + 1] - cell_start[row + bx0];
-        }
+      const int cnt = count_rows(by0, by1, bz0, bz1, grow);
       if (cnt >= K + 1 || (bx0 == 0 && by0 == 0 && bz0 == 0 && bx1 == G.g0 - 1 && by1 == G.g1 - 1 &&
                            bz1 == G.g2 - 1))
         break;
     }
-    for (int z = bz0; z <= bz1; ++z)
-      for (int y = by0; y <= by1; ++y) {
-        const int row = G.g0 * (y + G.g1 * z);
-        scan(cell_start[row + bx0], cell_start[row + bx1 + 1]);
-      }
+    scan_rows(by0, by1, bz0, bz1, grow);
   }
 
   if (kSortFill && filling) {  // fewer than K other points: sort what there is
