@@ -222,12 +222,13 @@ def main(argv=None) -> int:
     ncells = vt.grid_plan(n).ncells
     sbpp = sort_bytes_per_point(P.dtype.type, n, ncells)
     sort_gbs = sbpp * n / (ms_sort / 1e3) / 1e9
-    knn_q = sum(p["cells"] for p in st0["passes"])
-    knn_bytes = sum(p["cells"] * knn_bytes_per_query(p["k"]) for p in st0["passes"])
+    knn_q = sum(p["cells"] for p in st0["passes"] if p["k"] > 0)
+    knn_bytes = sum(p["cells"] * knn_bytes_per_query(p["k"]) for p in st0["passes"] if p["k"] > 0)
     if kmodel is not None:  # the feature pass is a 16-NN over every cell
         knn_q += n
         knn_bytes += n * knn_bytes_per_query(16)
-    knn_gbs = knn_bytes / ((ms_knn + ms_feat) / 1e3) / 1e9
+    # (the fused form, k0 = 0, has no k-NN pass)
+    knn_gbs = knn_bytes / ((ms_knn + ms_feat) / 1e3) / 1e9 if ms_knn + ms_feat > 0 else None
     flops = ALGO_FLOPS_PER_CELL.get(args.workload)
     clip_tf = flops * n / (ms_clip / 1e3) / 1e12 if flops else None
     stages = {
@@ -235,7 +236,8 @@ def main(argv=None) -> int:
                      frac=sort_gbs / PEAK["hbm_gbs"], ms=ms_sort,
                      per_unit=f"{sbpp:.2f} bytes per point (points read, records and perm written, cell starts)"),
         "knn": dict(bound="hbm", achieved=knn_gbs, peak=PEAK["hbm_gbs"], unit="GB/s",
-                    frac=knn_gbs / PEAK["hbm_gbs"], ms=ms_knn + ms_feat, queries=knn_q,
+                    frac=knn_gbs / PEAK["hbm_gbs"] if knn_gbs is not None else None, ms=ms_knn + ms_feat,
+                    queries=knn_q,
                     per_unit="16 + 4k bytes per query (record read, k indices written)"),
         "clip": dict(bound="alu", achieved=clip_tf, peak=PEAK["fp32_tflops"], unit="TFLOP/s",
                      frac=(clip_tf / PEAK["fp32_tflops"]) if clip_tf else None, ms=ms_clip,
