@@ -31,7 +31,12 @@ def grid_dims(n, lo, hi, pts_per_cell=2.0):
     return np.maximum(1, np.rint(ext * scale)).astype(np.int64)
 
 
-def features(points, lo=(0, 0, 0), hi=(1, 1, 1), rows=None) -> np.ndarray:
+def features(points, lo=(0, 0, 0), hi=(1, 1, 1), rows=None, nbr=None) -> np.ndarray:
+    """Features of points[rows] (all points by default).  The 16 nearest come
+    from a k-d tree in double, or, with ``nbr`` ([len(rows), 16] point indices
+    in ascending order of distance), from that list: the features of a given
+    neighbour list, for lists whose order at equal float distances is fixed
+    by another rule."""
     from scipy.spatial import cKDTree
 
     P = np.asarray(points, dtype=np.float64)
@@ -49,10 +54,14 @@ def features(points, lo=(0, 0, 0), hi=(1, 1, 1), rows=None) -> np.ndarray:
     nbar = n / G
     ell = np.cbrt(np.prod(ext) / n)
     rows = np.arange(n) if rows is None else np.asarray(rows)
-    tree = cKDTree(P)
-    kq = min(17, n)
-    dist, idx = tree.query(P[rows], k=kq)
-    dist, idx = dist.reshape(len(rows), kq)[:, 1:], idx.reshape(len(rows), kq)[:, 1:]
+    if nbr is None:
+        tree = cKDTree(P)
+        kq = min(17, n)
+        dist, idx = tree.query(P[rows], k=kq)
+        dist, idx = dist.reshape(len(rows), kq)[:, 1:], idx.reshape(len(rows), kq)[:, 1:]
+    else:
+        idx = np.asarray(nbr, dtype=np.int64)
+        dist = np.sqrt(((P[idx] - P[rows][:, None, :]) ** 2).sum(-1))
     F = np.zeros((len(rows), NFEAT))
     cr = c[rows]
     for s in range(3):

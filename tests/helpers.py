@@ -211,3 +211,18 @@ def face_errors(gpu_area, gpu_cen, orc, r2, rows=None, gpu_row_ptr=None, box_siz
     bar_c = CEN_RTOL * R + CEN_FLOOR * r2[rows] ** 2 / V
     rc = np.abs(c_g - c_o).max(axis=1) / bar_c
     return int((ra > 1).sum()), int((rc > 1).sum()), float(ra.max(initial=0)), float(rc.max(initial=0))
+
+
+def knn_ref_f32(S32, queries, k):
+    """k nearest by (d^2, sorted index), d^2 = (dx dx + dy dy) + dz dz in
+    float32 with every product and sum rounded on its own (numpy float32
+    ufuncs do not fuse)."""
+    out = np.full((len(queries), k), -1, np.int64)
+    for a in range(0, len(queries), 256):
+        q = queries[a:a + 256]
+        D = S32[None, :, :] - S32[q, None, :]
+        d2 = (D[..., 0] * D[..., 0] + D[..., 1] * D[..., 1]) + D[..., 2] * D[..., 2]
+        d2[np.arange(len(q)), q] = np.inf
+        idx = np.argsort(d2, axis=1, kind="stable")[:, :k]
+        out[a:a + 256] = idx
+    return out

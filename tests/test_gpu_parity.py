@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import triple_vertices, compare_rows, note, vertex_map, volume_errors
+from helpers import triple_vertices, compare_rows, note, vertex_map, volume_errors, knn_ref_f32
 from paper_2412_04514_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -213,21 +213,6 @@ def test_knn_f32_lists(kind):
         assert np.all(np.diff(d_got) >= -4e-7 * kth)
 
 
-def _knn_ref_f32(S32, queries, k):
-    """k nearest by (d^2, sorted index), d^2 = (dx dx + dy dy) + dz dz in
-    float32 with every product and sum rounded on its own (numpy float32
-    ufuncs do not fuse)."""
-    out = np.full((len(queries), k), -1, np.int64)
-    for a in range(0, len(queries), 256):
-        q = queries[a:a + 256]
-        D = S32[None, :, :] - S32[q, None, :]
-        d2 = (D[..., 0] * D[..., 0] + D[..., 1] * D[..., 1]) + D[..., 2] * D[..., 2]
-        d2[np.arange(len(q)), q] = np.inf
-        idx = np.argsort(d2, axis=1, kind="stable")[:, :k]
-        out[a:a + 256] = idx
-    return out
-
-
 @pytest.mark.parametrize("kind", ["uniform", "cluster", "filament"])
 @pytest.mark.parametrize("k", [32, 64])
 def test_knn_f32_keys_exact(kind, k):
@@ -241,7 +226,7 @@ def test_knn_f32_keys_exact(kind, k):
     S32 = srt[:, :3].cpu().numpy()
     q = np.sort(np.random.default_rng(1).choice(len(P), 1500, replace=False)).astype(np.int32)
     got = vt.knn(srt, grid, cs, k, queries=torch.from_numpy(q).cuda(), dist="f32").cpu().numpy()
-    assert np.array_equal(got, _knn_ref_f32(S32, q, k))
+    assert np.array_equal(got, knn_ref_f32(S32, q, k))
 
 
 def _tied_boundary_points(dtype, k=8, n_base=20_000, n_seeds=1500, seed=0):

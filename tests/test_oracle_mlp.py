@@ -122,6 +122,27 @@ def test_features_against_brute_force():
         np.testing.assert_allclose(F[k], _brute_features(P, i, np.zeros(3), np.ones(3)), rtol=1e-10, atol=1e-12)
 
 
+def test_features_of_a_given_list():
+    """With the k-d tree's own 16-nearest list passed in, the list path gives
+    the same features; a list in another order of equal distances moves only
+    the order-free features' rounding."""
+    rng = np.random.default_rng(9)
+    P = np.concatenate([rng.random((300, 3)), 0.6 + 0.02 * rng.normal(size=(100, 3))])
+    P = np.clip(P, 0, 1)
+    rows = np.arange(0, 400, 5)
+    d2 = ((P[rows][:, None, :] - P[None, :, :]) ** 2).sum(-1)
+    d2[np.arange(len(rows)), rows] = np.inf
+    nbr = np.argsort(d2, axis=1, kind="stable")[:, :16]
+    np.testing.assert_allclose(ofeat.features(P, rows=rows, nbr=nbr), ofeat.features(P, rows=rows),
+                               rtol=1e-12, atol=1e-14)
+    # the first 15 reversed: d_4, d_8 and d_1 read other entries, the rest is order-free
+    rev = np.concatenate([nbr[:, :15][:, ::-1], nbr[:, 15:]], axis=1)
+    a, b = ofeat.features(P, rows=rows, nbr=rev), ofeat.features(P, rows=rows)
+    keep = [0, 1, 2, 5, 6, 8, 9, 10, 11]
+    np.testing.assert_allclose(a[:, keep], b[:, keep], rtol=1e-10, atol=1e-12)
+    assert not np.allclose(a[:, 3], b[:, 3])
+
+
 def test_features_closed_forms():
     # two points in every grid cell of a 6^3 grid: block occupancy ratio 1 -> log2(2)
     g = 6
