@@ -222,11 +222,17 @@ def main(argv=None) -> int:
     ncells = vt.grid_plan(n).ncells
     sbpp = sort_bytes_per_point(P.dtype.type, n, ncells)
     sort_gbs = sbpp * n / (ms_sort / 1e3) / 1e9
-    knn_q = sum(p["cells"] for p in st0["passes"] if p["k"] > 0)
-    knn_bytes = sum(p["cells"] * knn_bytes_per_query(p["k"]) for p in st0["passes"] if p["k"] > 0)
-    if kmodel is not None:  # the feature pass is a 16-NN over every cell
-        knn_q += n
-        knn_bytes += n * knn_bytes_per_query(16)
+    if kmodel is not None:
+        # the learned form runs one k-NN at the largest bucket over every cell
+        # (its rows' prefixes serve the features and the smaller buckets),
+        # then retries of their own above it
+        kl = max(vt.BUCKETS)
+        knn_q = n + sum(p["cells"] for p in st0["passes"] if p["k"] > kl)
+        knn_bytes = n * knn_bytes_per_query(kl) + sum(p["cells"] * knn_bytes_per_query(p["k"])
+                                                      for p in st0["passes"] if p["k"] > kl)
+    else:
+        knn_q = sum(p["cells"] for p in st0["passes"] if p["k"] > 0)
+        knn_bytes = sum(p["cells"] * knn_bytes_per_query(p["k"]) for p in st0["passes"] if p["k"] > 0)
     # (the fused form, k0 = 0, has no k-NN pass)
     knn_gbs = knn_bytes / ((ms_knn + ms_feat) / 1e3) / 1e9 if ms_knn + ms_feat > 0 else None
     flops = ALGO_FLOPS_PER_CELL.get(args.workload)

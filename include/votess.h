@@ -230,7 +230,10 @@ typedef struct {
   double pts_per_cell;      /* grid density (default 2) */
   votess_precision precision;
   double eps;               /* default 1e-6 */
-  votess_kmodel* kmodel;    /* learned-k: per-cell list size from the network (nullable) */
+  votess_kmodel* kmodel;    /* learned-k: per-cell list size from the network (nullable).  The
+                               first pass lists the 64 nearest of every cell once; the features
+                               read each list's first 16 entries and a cell in bucket k is
+                               clipped by its list's first k entries */
   double tau;               /* learned-k decision threshold (default 0.9) */
   int32_t want_vertices;    /* 1: also return vertices */
   int32_t index_space;      /* 0: original indices (default), 1: sorted indices */

@@ -52,6 +52,8 @@ struct ClipArgs {
   int nc;
   const int* knn;
   int k;
+  int kstride;    // entries per list row
+  int knn_by_id;  // list row of a cell: its sorted id (else its position in cells)
   double eps;
   double dmargin;  // applied to d^2 in certificate tests (k-lists built in float)
   int max_nbr, max_vert, out_by_id;
@@ -672,7 +674,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   // The list is read two planes ahead (the index of plane m+2, the record of
   // plane m+1), so that the two dependent loads of a plane overlap the work
   // of the one before it.
-  const int* klist = a.knn + (size_t)(have ? t_idx : 0) * a.k;
+  const int* klist = a.knn + (size_t)(have ? (a.knn_by_id ? (long long)sid : t_idx) : 0) * a.kstride;
   int nb_next = have && a.k > 0 ? klist[0] : -1;
   Rec4 q_next = rec[nb_next >= 0 ? nb_next : sid];
   int nb_next2 = have && a.k > 1 ? klist[1] : -1;
@@ -740,7 +742,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     if (__any(need)) {
       const double r64 = radius64(need);
       if (need) {
-        const Rec4 q = rec[a.knn[(size_t)t_idx * a.k + a.k - 1]];
+        const Rec4 q = rec[klist[a.k - 1]];
         const V3<double> n64 = {(double)q.x - p64x, (double)q.y - p64y, (double)q.z - p64z};
         const double d64 = dot(n64, n64);
         fprev = d64 * kDmargin > 4.0 * r64;
@@ -771,7 +773,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
   // fused form, with no k-NN pass and no list in memory.
   if constexpr (STREAM) {
     const bool nolist = a.k == 0;
-    const int ik0 = (have && st == VOTESS_CELL_RADIUS && !nolist) ? a.knn[(size_t)t_idx * a.k + a.k - 1] : -1;
+    const int ik0 = (have && st == VOTESS_CELL_RADIUS && !nolist) ? klist[a.k - 1] : -1;
     const bool strm = have && st == VOTESS_CELL_RADIUS && (nolist || ik0 >= 0);  // a full list that did not certify
     if (strm) st = ST_RUN;
     if constexpr (kVrad) {
@@ -1503,6 +1505,8 @@ votess_status launch_clip(const ClipLaunch& a, hipStream_t st) {
   c.nc = a.nc;
   c.knn = a.knn;
   c.k = a.k;
+  c.kstride = a.knn_stride > 0 ? a.knn_stride : a.k;
+  c.knn_by_id = a.knn_by_id;
   c.eps = a.eps;
   // k-lists ordered by float distances may misplace near-ties by a few ulp:
   // certify only with that much slack

@@ -119,6 +119,8 @@ struct ClipLaunch {
   int nc;
   const int32_t* knn;
   int k;
+  int knn_stride = 0;  // entries per list row (0: k); a row may be longer than the k entries used
+  int knn_by_id = 0;   // 1: list row of a cell = its sorted id (else its position in `cells`)
   votess_precision precision;
   double eps;
   votess_dtype knn_dist;

@@ -94,7 +94,8 @@ __device__ void eig3(double a00, double a01, double a02, double a11, double a12,
 template <typename T>
 __global__ __launch_bounds__(256) void k_features(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
                                                   const int* __restrict__ cell_start, const int* __restrict__ queries,
-                                                  int nq, const int* __restrict__ knn16, float* __restrict__ feats) {
+                                                  int nq, const int* __restrict__ knn16, int kstride,
+                                                  float* __restrict__ feats) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nq) return;
   const int s = queries ? queries[q] : q;
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void k_features(const typename Rec<T>::type* _
     const double c = (double)(x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1);
     f[sc] = (float)log2(1.0 + (double)cnt / (nbar * c));
   }
-  const int* L = knn16 + (size_t)q * 16;
+  const int* L = knn16 + (size_t)q * kstride;  // the row's first 16 entries
   double d[16], ox[16], oy[16], oz[16];
   int m = 0;
   for (int i = 0; i < 16; ++i) {
@@ -529,9 +530,9 @@ votess_status run_features(votess_ctx* ctx, const void* sorted, votess_dtype dt,
                     dt == VOTESS_F32 ? VOTESS_F32 : VOTESS_F64, knn16, st));
   const unsigned b = (unsigned)((nq + 255) / 256);
   if (dt == VOTESS_F32)
-    k_features<float><<<b, 256, 0, st>>>((const float4*)sorted, n, G, cell_start, queries, nq, knn16, feats);
+    k_features<float><<<b, 256, 0, st>>>((const float4*)sorted, n, G, cell_start, queries, nq, knn16, 16, feats);
   else
-    k_features<double><<<b, 256, 0, st>>>((const double4*)sorted, n, G, cell_start, queries, nq, knn16, feats);
+    k_features<double><<<b, 256, 0, st>>>((const double4*)sorted, n, G, cell_start, queries, nq, knn16, 16, feats);
   VT_HIP(hipGetLastError());
   return VOTESS_OK;
 }
@@ -584,37 +585,58 @@ static votess_status run_grad(votess_kmodel* km, const float* feats, const uint8
 votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau, const void* sorted, int n,
                                  const votess_grid& grid, const int32_t* cell_start, const ClipLaunch& base,
                                  int stream, int32_t* cells_buf, votess_stats& S, hipStream_t st) {
+  // The k-NN runs once, at the largest bucket, for every cell: a row is
+  // sorted by (d^2, sorted index), so its first 16 entries are the cell's
+  // 16-NN list (the features' input) and its first k entries the k-list of
+  // a cell the network puts in bucket k.  A separate 16-NN pass would cost
+  // about a third of this one, more than the shorter lists of the smaller
+  // buckets save.
   const GridDev G = to_dev(grid);
   const votess_dtype dist = base.knn_dist;
-  void* knn16 = dev_alloc(ctx, (size_t)n * 16 * 4);
+  const int KL = votess_buckets[NO - 1];
+  void* knn = dev_alloc(ctx, (size_t)n * KL * 4);
   void* feats = dev_alloc(ctx, (size_t)n * NF * 4);
   void* bucket = dev_alloc(ctx, (size_t)n);
-  void* knnb = dev_alloc(ctx, (size_t)n * 64 * 4);
+  void* failbuf = dev_alloc(ctx, (size_t)n * 4);
   auto cleanup = [&]() {
-    dev_free(ctx, knn16);
+    dev_free(ctx, knn);
     dev_free(ctx, feats);
     dev_free(ctx, bucket);
-    dev_free(ctx, knnb);
+    dev_free(ctx, failbuf);
   };
-  if (!knn16 || !feats || !bucket || !knnb) {
+  if (!knn || !feats || !bucket || !failbuf) {
     cleanup();
     return fail(VOTESS_ENOMEM, "learned pass buffers");
   }
-  hipEvent_t e0, e1, e2;
+  hipEvent_t e0, e1, e2, e3;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   (void)hipEventCreate(&e2);
+  (void)hipEventCreate(&e3);
   (void)hipEventRecord(e0, st);
-  votess_status rc = run_features(ctx, sorted, base.dtype, n, G, cell_start, base.sub, nullptr, n,
-                                  (int32_t*)knn16, (float*)feats, st);
+  votess_status rc =
+      launch_knn(ctx, sorted, base.dtype, n, G, cell_start, base.sub, nullptr, n, KL, dist, (int32_t*)knn, st);
   (void)hipEventRecord(e1, st);
-  if (rc == VOTESS_OK) rc = run_choose(km, (const float*)feats, n, (float)tau, (uint8_t*)bucket, nullptr, st);
+  if (rc == VOTESS_OK && n > 0) {
+    const unsigned b = (unsigned)((n + 255) / 256);
+    if (base.dtype == VOTESS_F32)
+      k_features<float><<<b, 256, 0, st>>>((const float4*)sorted, n, G, cell_start, nullptr, n, (const int*)knn, KL,
+                                           (float*)feats);
+    else
+      k_features<double><<<b, 256, 0, st>>>((const double4*)sorted, n, G, cell_start, nullptr, n, (const int*)knn,
+                                            KL, (float*)feats);
+    if (hipGetLastError() != hipSuccess) rc = fail(VOTESS_EHIP, "learned pass: feature kernel launch");
+  }
   (void)hipEventRecord(e2, st);
-  (void)hipEventSynchronize(e2);
+  if (rc == VOTESS_OK) rc = run_choose(km, (const float*)feats, n, (float)tau, (uint8_t*)bucket, nullptr, st);
+  (void)hipEventRecord(e3, st);
+  (void)hipEventSynchronize(e3);
   float ms = 0;
   (void)hipEventElapsedTime(&ms, e0, e1);
-  S.ms_features += ms;
+  S.ms_knn += ms;
   (void)hipEventElapsedTime(&ms, e1, e2);
+  S.ms_features += ms;
+  (void)hipEventElapsedTime(&ms, e2, e3);
   S.ms_mlp += ms;
   int64_t entered_prev = 0;
   if (base.counters) {
@@ -638,28 +660,25 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
     if (cnt == 0) continue;
     const int k = votess_buckets[b];
     (void)hipEventRecord(e0, st);
-    rc = launch_knn(ctx, sorted, base.dtype, n, G, cell_start, base.sub, cells_buf, cnt, k, dist, (int32_t*)knnb, st);
-    (void)hipEventRecord(e1, st);
-    if (rc != VOTESS_OK) break;
     ClipLaunch c = base;
     c.cells = cells_buf;
     c.nc = cnt;
-    c.knn = (const int32_t*)knnb;
+    c.knn = (const int32_t*)knn;
     c.k = k;
+    c.knn_stride = KL;
+    c.knn_by_id = 1;
     c.stream = stream;
     rc = launch_clip(c, st);
-    (void)hipEventRecord(e2, st);
-    (void)hipEventSynchronize(e2);
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
     (void)hipEventElapsedTime(&ms, e0, e1);
-    S.ms_knn += ms;
-    (void)hipEventElapsedTime(&ms, e1, e2);
     S.ms_clip += ms;
     if (rc != VOTESS_OK) break;
     // cells of this bucket still uncertified after the pass, and cells its
     // lists left uncertified that went on into the stream phase
     int nfail = 0;
     unsigned long long entered = 0;
-    rc = launch_compact_failed(base.status, cells_buf, cnt, (int32_t*)knnb, ctx->d_counter,
+    rc = launch_compact_failed(base.status, cells_buf, cnt, (int32_t*)failbuf, ctx->d_counter,
                                (uint8_t)((1u << VOTESS_CELL_RADIUS) | (1u << VOTESS_CELL_CAPACITY)), ctx->ws, st);
     if (rc != VOTESS_OK) break;
     if (hipMemcpyAsync(&nfail, ctx->d_counter, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -680,6 +699,7 @@ votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);
+  (void)hipEventDestroy(e3);
   cleanup();
   return rc;
 }
