@@ -123,15 +123,17 @@ struct GroupList {
   }
 };
 
-// Held to 5 waves per SIMD (96 VGPRs, ~100 bytes per lane of spills): the
-// search is latency-bound, and the fifth wave measured ~8% faster than four.
+// Held to 6 waves per SIMD (80 VGPRs, 100-140 bytes per lane of spills): the
+// search is latency-bound; at k = 64 on clustered input six waves measured 4%
+// faster than five (and 10% faster than four, without spills), seven and
+// eight slower again.
 // Blocks are taken in an XCD-aware order: the hardware deals launched
 // blocks round-robin over the eight XCDs, so launched block b runs logical
 // block (b mod 8) per + b / 8 (per = blocks / 8, rounded up; the launch is
 // padded to 8 per) and each XCD works on one contiguous stretch of the
 // grid-sorted queries, whose candidates its own L2 then holds.
 template <typename T, typename D, int K, int GS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_knn(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_knn(const typename Rec<T>::type* __restrict__ rec, int n, GridDev G,
                                              const int* __restrict__ cell_start, SubGrid sub,
                                              const int* __restrict__ queries, int nq, int* __restrict__ knn,
                                              unsigned* __restrict__ err, int nblocks) {
