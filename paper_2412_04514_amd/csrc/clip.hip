@@ -796,6 +796,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       const Rec4 q = rec[ik];
       dk2 = dist2_nc((R)q.x - px, (R)q.y - py, (R)q.z - pz);
     }
+    // A box (seed-relative bounds, already widened by gmarg) that lies inside
+    // the list's ball holds list members only: every point in it is closer
+    // than the list's last one even after the rounding of d^2.
+    const double dk2in = (double)dk2 * (1.0 - 1e-6);
+    auto in_list_ball = [&](double ax, double bx, double ay, double by, double az, double bz) -> bool {
+      const double f = fmax(ax * ax, bx * bx) + fmax(ay * ay, by * by) + fmax(az * az, bz * bz);
+      return f < dk2in;
+    };
     // flower box in grid cells, from the current vertices (group reduction)
     Enum& E_ = senum[STREAM ? g : 0];
     int &fb0 = E_.fb0, &fb1 = E_.fb1, &fb2 = E_.fb2, &fb3 = E_.fb3, &fb4 = E_.fb4, &fb5 = E_.fb5;
@@ -906,6 +914,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     };
     auto relevant = [&](unsigned char* out, double x0, double x1, double y0, double y1, double z0,
                         double z1) -> int {
+      if (in_list_ball(x0 - p64x - gmarg, x1 - p64x + gmarg, y0 - p64y - gmarg, y1 - p64y + gmarg, z0 - p64z - gmarg,
+                       z1 - p64z + gmarg))
+        return 0;  // (group-uniform)
       const R ax = out_lo(x0 - p64x - gmarg), bx = out_hi(x1 - p64x + gmarg);
       const R ay = out_lo(y0 - p64y - gmarg), by = out_hi(y1 - p64y + gmarg);
       const R az = out_lo(z0 - p64z - gmarg), bz = out_hi(z1 - p64z + gmarg);
@@ -931,8 +942,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     };
     int nR = 0, nD = 0;
     bool okR = false, okD = false;  // lists valid for the current vertices
-    // does sub-row (sy, sz) of the dense cell's sub-block meet the ball of a
-    // vertex of the cell's list?  (one sub-row per lane)
+    // can sub-row (sy, sz) of the dense cell's sub-block hold a cutting point:
+    // not inside the list's ball, and (while the dense cell's vertex list is
+    // valid) meeting the ball of a listed vertex?  (one sub-row per lane)
     auto sub_row_relevant = [&](int sy, int sz) -> bool {
       const double* dgp = dgeo + g * 9;
       const int m2 = a.sub.start[dsto + 2];
@@ -942,6 +954,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       const double Y1 = sy == dm1 - 1 ? dgp[1] + Gd.h1 : dgp[4] + (sy + 1) * dgp[7];
       const double Z0 = sz == 0 ? dgp[2] : dgp[5] + sz * dgp[8];
       const double Z1 = sz == m2 - 1 ? dgp[2] + Gd.h2 : dgp[5] + (sz + 1) * dgp[8];
+      if (in_list_ball(X0 - p64x - gmarg, X1 - p64x + gmarg, Y0 - p64y - gmarg, Y1 - p64y + gmarg, Z0 - p64z - gmarg,
+                       Z1 - p64z + gmarg))
+        return false;
+      if (!okD) return true;
       const R ax = out_lo(X0 - p64x - gmarg), bx = out_hi(X1 - p64x + gmarg);
       const R ay = out_lo(Y0 - p64y - gmarg), by = out_hi(Y1 - p64y + gmarg);
       const R az = out_lo(Z0 - p64z - gmarg), bz = out_hi(Z1 - p64z + gmarg);
@@ -990,7 +1006,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
                     const int qz = q / kyn, qy = q - qz * kyn;
                     const int sz = dq2 + ((qz & 1) ? (qz + 1) >> 1 : -(qz >> 1));
                     const int sy = dq1 + ((qy & 1) ? (qy + 1) >> 1 : -(qy >> 1));
-                    if (sz >= dsz0 && sz <= dsz1 && sy >= dsy0 && sy <= dsy1 && (!okD || sub_row_relevant(sy, sz))) {
+                    if (sz >= dsz0 && sz <= dsz1 && sy >= dsy0 && sy <= dsy1 && sub_row_relevant(sy, sz)) {
                       const int rowb = kSubHead + dm0 * (sy + dm1 * sz);
                       lo = a.sub.start[dsto + rowb + dsx0];
                       hi = a.sub.start[dsto + rowb + dsx1 + 1];
