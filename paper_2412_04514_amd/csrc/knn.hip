@@ -257,13 +257,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
   };
   // scans the rows (y, z) of a block [y0, y1] x [z0, z1]: row_range(y, z)
   // gives a row's point range; GS rows at a time, one per lane, listed and
-  // scanned together
-  auto scan_rows = [&](int y0, int y1, int z0, int z1, auto row_range) {
-    const int ny = y1 - y0 + 1, npairs = ny * (z1 - z0 + 1);
+  // scanned together.  Rows go outward from row (yc, zc) (offsets 0, +1, -1,
+  // +2, ... in z, and in y within each z), so that the list's first K
+  // candidates lie near the query and fewer later ones displace them.
+  auto scan_rows = [&](int y0, int y1, int z0, int z1, int yc, int zc, auto row_range) {
+    const int ny = 2 * max(yc - y0, y1 - yc) + 1, npairs = ny * (2 * max(zc - z0, z1 - zc) + 1);
     for (int pb = 0; pb < npairs; pb += GS) {
       const int pi = pb + l;
       int2 rg = make_int2(0, 0);
-      if (pi < npairs) rg = row_range(y0 + pi % ny, z0 + pi / ny);
+      if (pi < npairs) {
+        const int kz = pi / ny, ky = pi - kz * ny;
+        const int z = zc + ((kz & 1) ? (kz + 1) >> 1 : -(kz >> 1));
+        const int y = yc + ((ky & 1) ? (ky + 1) >> 1 : -(ky >> 1));
+        if (z >= z0 && z <= z1 && y >= y0 && y <= y1) rg = row_range(y, z);
+      }
       const bool k0 = rg.x < rg.y;
       const unsigned long long b0 = (__ballot(k0) >> gb) & gmask;
       if (k0) grng[__popcll(b0 & ((1ull << l) - 1ull))] = rg;
@@ -316,7 +323,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                            bz1 == sc.m2 - 1))
         break;
     }
-    scan_rows(by0, by1, bz0, bz1, srow);
+    scan_rows(by0, by1, bz0, bz1, qy, qz, srow);
   } else {
     auto grow = [&](int y, int z) {
       const int row = G.g0 * (y + G.g1 * z);
@@ -331,7 +338,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                            bz1 == G.g2 - 1))
         break;
     }
-    scan_rows(by0, by1, bz0, bz1, grow);
+    scan_rows(by0, by1, bz0, bz1, cy, cz, grow);
   }
 
   if (kSortFill && filling) {  // fewer than K other points: sort what there is
