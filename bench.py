@@ -60,23 +60,33 @@ def clip_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def clip_traffic(workload: str):
-    """HBM bytes per step of all k_clip launches from the committed counter
-    summary, only while it was taken on the clip kernel as it stands (the
-    summary records the SHA-256 of the sources the kernel is compiled from);
-    None otherwise."""
-    prof = os.path.join(ROOT, "profiles", f"clip_traffic_{workload.replace('-', '')}.md")
+def clip_traffic_profile(workload: str) -> str:
+    """Path of the committed counter summary of a workload's clip traffic
+    (cluster-16m-f32 -> profiles/clip_traffic_cluster16m_f32.md)."""
+    return os.path.join(ROOT, "profiles", f"clip_traffic_{workload.replace('-', '', 1).replace('-', '_')}.md")
+
+
+def clip_traffic_fields(workload: str) -> dict:
+    """The '- key: value' lines of that summary (empty if it is missing)."""
     try:
-        text = open(prof).read()
+        text = open(clip_traffic_profile(workload)).read()
     except OSError:
-        return None
-    sha = clip_sources_sha256()
+        return {}
     vals = {}
     for ln in text.splitlines():
         if ":" in ln and ln.strip().startswith("- "):
             k, v = ln.strip()[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("clip sources sha256") != sha:
+    return vals
+
+
+def clip_traffic(workload: str):
+    """HBM bytes per step of all k_clip launches from the committed counter
+    summary, only while it was taken on the clip kernel as it stands (the
+    summary records the SHA-256 of the sources the kernel is compiled from);
+    None otherwise."""
+    vals = clip_traffic_fields(workload)
+    if vals.get("clip sources sha256") != clip_sources_sha256():
         return None
     try:
         return float(vals["bytes per step"])
