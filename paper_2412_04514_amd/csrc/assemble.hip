@@ -85,43 +85,63 @@ __global__ void k_rows_count(const int* __restrict__ nbr_count, const int* __res
   counts[sorted_space ? s : perm[s]] = nbr_count[s];
 }
 
-// One thread per row: the row's neighbour ids (mapped to the output index
-// space) are staged in LDS, column-major so that the block's threads hit
-// distinct banks, and each id goes straight to its rank in the row (equal
-// ids, which a periodic row may hold, are ranked by position), so every
-// output is written once.  Areas move with their ids; centroids with their
-// rows.
-constexpr int kFillBlock = 64;
-template <int MAXN>
+// A group of 16 lanes per row (rows of at most 64 entries, four per lane):
+// the lanes read the row's neighbour ids in one coalesced load, map them to
+// the output index space, stage them in LDS, and rank each of their entries
+// against the whole row (equal ids, which a periodic row may hold, are
+// ranked by position); the group then writes its row with one store to
+// contiguous addresses, so that each output row reaches L2 whole rather than
+// one id at a time from rows scattered over the array.  Areas move with
+// their ids; volumes and centroids with their rows.
+constexpr int kFillBlock = 256;
+constexpr int kFillLanes = 16;
+constexpr int kFillMax = 64;
 __global__ __launch_bounds__(kFillBlock) void k_rows_fill(
     const int* __restrict__ nbr_count, const int* __restrict__ nbr, int max_nbr, const int* __restrict__ perm,
     const double* __restrict__ vol_sorted, const double* __restrict__ area_sorted,
     const double* __restrict__ cen_sorted, int n, int sorted_space, const long long* __restrict__ row_ptr,
     int* __restrict__ col, double* __restrict__ volume, double* __restrict__ area, double* __restrict__ centroid) {
-  __shared__ int ids[MAXN * kFillBlock];
-  const int tid = threadIdx.x;
-  const int s = blockIdx.x * kFillBlock + tid;
-  if (s >= n) return;
+  constexpr int R = kFillBlock / kFillLanes, J = kFillMax / kFillLanes;
+  __shared__ int ids[R * kFillMax];
+  const int l = threadIdx.x & (kFillLanes - 1), g = threadIdx.x / kFillLanes;
+  const int s = blockIdx.x * R + g;
+  if (s >= n) return;  // whole groups leave together
   const int r = sorted_space ? s : perm[s];
-  volume[r] = vol_sorted[s];
-  if (centroid)
-    for (int a = 0; a < 3; ++a) centroid[(size_t)r * 3 + a] = cen_sorted[(size_t)s * 3 + a];
+  if (l == 0) volume[r] = vol_sorted[s];
+  if (centroid && l < 3) centroid[(size_t)r * 3 + l] = cen_sorted[(size_t)s * 3 + l];
   // a row longer than the staging stride (a host-fallback cell) is written
   // by the host
-  if (nbr_count[s] > max_nbr) return;
   const int cnt = nbr_count[s];
+  if (cnt > max_nbr) return;
   const int* src = nbr + (size_t)s * max_nbr;
-  for (int e = 0; e < cnt; ++e) ids[e * kFillBlock + tid] = sorted_space ? src[e] : perm[src[e]];
-  const long long o = row_ptr[r];
-  for (int e = 0; e < cnt; ++e) {
-    const int v = ids[e * kFillBlock + tid];
-    int rank = 0;
-    for (int x = 0; x < cnt; ++x) {
-      const int w = ids[x * kFillBlock + tid];
-      rank += w < v || (w == v && x < e);
+  int* row = ids + g * kFillMax;
+  int v[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int e = l + j * kFillLanes;
+    v[j] = 0;
+    if (e < cnt) {
+      v[j] = sorted_space ? src[e] : perm[src[e]];
+      row[e] = v[j];
     }
-    col[o + rank] = v;
-    if (area) area[o + rank] = area_sorted[(size_t)s * max_nbr + e];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  int rank[J] = {};
+  const int nj = (cnt + kFillLanes - 1) / kFillLanes;
+  for (int x = 0; x < cnt; ++x) {
+    const int w = row[x];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      if (j < nj) rank[j] += w < v[j] || (w == v[j] && x < l + j * kFillLanes);
+  }
+  const long long o = row_ptr[r];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int e = l + j * kFillLanes;
+    if (e < cnt) {
+      col[o + rank[j]] = v[j];
+      if (area) area[o + rank[j]] = area_sorted[(size_t)s * max_nbr + e];
+    }
   }
 }
 
@@ -193,10 +213,11 @@ votess_status launch_assemble(const int32_t* nbr_count, const int32_t* nbr, int 
     ws.used = mark;
     return VOTESS_OK;
   }
-  if (max_nbr > 64) return fail(VOTESS_EINVAL, "assemble: rows longer than 64");
+  if (max_nbr > kFillMax) return fail(VOTESS_EINVAL, "assemble: rows longer than %d", kFillMax);
   if ((area && !area_sorted) || (centroid && !cen_sorted)) return fail(VOTESS_EINVAL, "assemble: null face input");
   if (n > 0) {  // phase 2: fill
-    k_rows_fill<64><<<(unsigned)((n + kFillBlock - 1) / kFillBlock), kFillBlock, 0, st>>>(
+    constexpr int rows_per_block = kFillBlock / kFillLanes;
+    k_rows_fill<<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kFillBlock, 0, st>>>(
         nbr_count, nbr, max_nbr, perm, vol_sorted, area_sorted, cen_sorted, n, index_space,
         (const long long*)row_ptr, col, volume, area, centroid);
     VT_HIP(hipGetLastError());
