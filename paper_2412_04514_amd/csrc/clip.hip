@@ -804,7 +804,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       const double f = fmax(ax * ax, bx * bx) + fmax(ay * ay, by * by) + fmax(az * az, bz * bz);
       return f < dk2in;
     };
-    // flower box in grid cells, from the current vertices (group reduction)
+    // A vertex whose widened ball reaches less than the list's ball from the
+    // seed (twice its radius below that ball's) can only hold list members:
+    // the flower box and the per-box vertex lists leave it out.
+    const R rlim = dk2in > 0.0 ? (R)(0.5 * sqrt(dk2in) * (1.0 - 1e-6)) : R(-1);
+    // flower box in grid cells, from the current vertices whose ball leaves
+    // the list's ball (group reduction)
     Enum& E_ = senum[STREAM ? g : 0];
     int &fb0 = E_.fb0, &fb1 = E_.fb1, &fb2 = E_.fb2, &fb3 = E_.fb3, &fb4 = E_.fb4, &fb5 = E_.fb5;
     fb0 = 0; fb1 = -1; fb2 = 0; fb3 = -1; fb4 = 0; fb5 = -1;
@@ -813,8 +818,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
       double mn0 = 1e300, mn1 = 1e300, mn2 = 1e300, mx0 = -1e300, mx1 = -1e300, mx2 = -1e300;
       for (int t = j; t < H; t += L) {
         if (tri[vb + t] == kEmpty) continue;
+        const R rv = vball(t, vx[vb + t], vy[vb + t], vz[vb + t]);
+        if (rv < rlim) continue;
         const double X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
-        const double rad = vball(t, vx[vb + t], vy[vb + t], vz[vb + t]);
+        const double rad = rv;
         mn0 = fmin(mn0, X - rad); mx0 = fmax(mx0, X + rad);
         mn1 = fmin(mn1, Y - rad); mx1 = fmax(mx1, Y + rad);
         mn2 = fmin(mn2, Z - rad); mx2 = fmax(mx2, Z + rad);
@@ -824,6 +831,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
         mn0 = fmin(mn0, shfl_xor_w(mn0, o, L)); mx0 = fmax(mx0, shfl_xor_w(mx0, o, L));
         mn1 = fmin(mn1, shfl_xor_w(mn1, o, L)); mx1 = fmax(mx1, shfl_xor_w(mx1, o, L));
         mn2 = fmin(mn2, shfl_xor_w(mn2, o, L)); mx2 = fmax(mx2, shfl_xor_w(mx2, o, L));
+      }
+      if (mn0 > mx0) {  // every ball inside the list's: the seed's own cell closes the scan
+        mn0 = mx0 = mn1 = mx1 = mn2 = mx2 = 0.0;
       }
       const double fw0 = p64x + mn0 - gmarg, fw1 = p64x + mx0 + gmarg;
       const double fw2 = p64y + mn1 - gmarg, fw3 = p64y + mx1 + gmarg;
@@ -929,7 +939,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
           const R rv = vball(t, X, Y, Z);
           const R gx = fmax(R(0), fmax(ax - X, X - bx)), gy = fmax(R(0), fmax(ay - Y, Y - by)),
                   gz = fmax(R(0), fmax(az - Z, Z - bz));
-          if (gx * gx + gy * gy + gz * gz <= rv * rv) bits |= 1u << s2;
+          if (rv >= rlim && gx * gx + gy * gy + gz * gz <= rv * rv) bits |= 1u << s2;
         }
       }
       int tot;
