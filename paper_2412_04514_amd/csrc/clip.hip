@@ -871,16 +871,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     int myj = -1;
     R myd2 = R(0);
     const R skip_scale = RECHECK ? R(1) - R(2e-6) : R(1) - R(1e-12);
-    // box of the current vertices (relative to the seed, widened by their
-    // error bounds): a candidate d can cut only if some vertex v has
-    // d.v > |d|^2 / 2, and max_v d.v <= sum_a max(d_a lo_a, d_a hi_a).  The
-    // cell only shrinks, so an older box is still a valid bound.
+    // box of the current vertices whose ball leaves the list's ball
+    // (relative to the seed, widened by their error bounds): a candidate d
+    // beyond the list can cut only if such a vertex v has d.v > |d|^2 / 2,
+    // and max_v d.v <= sum_a max(d_a lo_a, d_a hi_a).  The cell only
+    // shrinks: a d that cuts the smaller cell cuts the larger one at some
+    // vertex, whose ball then holds d, a point beyond the list, so that
+    // vertex was in the older box, which is still a valid bound.
     R bl0 = 0, bl1 = 0, bl2 = 0, bh0 = 0, bh1 = 0, bh2 = 0;
     bool box_ok = false;
     auto vertex_box = [&]() {
       R a0 = R(3.0e38), a1 = R(3.0e38), a2 = R(3.0e38), b0 = R(-3.0e38), b1 = R(-3.0e38), b2 = R(-3.0e38);
       for (int t = j; t < H; t += L) {
         if (tri[vb + t] == kEmpty) continue;
+        if (vball(t, vx[vb + t], vy[vb + t], vz[vb + t]) < rlim) continue;
         const R e = RECHECK ? (R)verr[vb + t] : R(0);
         const R X = vx[vb + t], Y = vy[vb + t], Z = vz[vb + t];
         a0 = fmin(a0, X - e); b0 = fmax(b0, X + e);
