@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kFillBlock) void k_rows_fill(
     const double* __restrict__ cen_sorted, int n, int sorted_space, const long long* __restrict__ row_ptr,
     int* __restrict__ col, double* __restrict__ volume, double* __restrict__ area, double* __restrict__ centroid) {
   constexpr int R = kFillBlock / kFillLanes, J = kFillMax / kFillLanes;
-  __shared__ int ids[R * kFillMax];
+  __shared__ int ids[R * (kFillMax + 1)];  // rows padded by a word: the groups' rows start in distinct banks
   const int l = threadIdx.x & (kFillLanes - 1), g = threadIdx.x / kFillLanes;
   const int s = blockIdx.x * R + g;
   if (s >= n) return;  // whole groups leave together
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kFillBlock) void k_rows_fill(
   const int cnt = nbr_count[s];
   if (cnt > max_nbr) return;
   const int* src = nbr + (size_t)s * max_nbr;
-  int* row = ids + g * kFillMax;
+  int* row = ids + g * (kFillMax + 1);
   int v[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {

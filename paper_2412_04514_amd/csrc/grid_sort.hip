@@ -26,7 +26,7 @@ GridDev to_dev(const votess_grid& g) {
 namespace {
 
 constexpr int kLdsSortMax = 4096; // larger cells sort their keys in global memory
-constexpr int kDenseBlocks = 1024; // blocks of the dense-cell pass (grid-stride over the dense cells)
+constexpr int kDenseBlocks = 2048; // blocks of the dense-cell pass (grid-stride over the dense cells)
 
 template <typename T>
 __global__ void k_cell_rank(const T* __restrict__ pts, int n, GridDev G, int* __restrict__ count,
