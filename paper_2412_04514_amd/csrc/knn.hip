@@ -37,8 +37,12 @@ struct KeyOps<float> {
   __device__ static double d2(Key a) { return (double)__uint_as_float((unsigned)(a >> 32)); }
   __device__ static int idx(Key a) { return a == ~0ull ? -1 : (int)(unsigned)(a & 0xffffffffu); }
   __device__ static Key shfl(Key a, int src) { return __shfl(a, src, 64); }
-  __device__ static Key shfl_xor(Key a, int m) { return __shfl_xor(a, m, 64); }
   __device__ static Key pick(bool c, Key a, Key b) { return c ? a : b; }
+  // f applied to each 32-bit word of the key
+  template <class F>
+  __device__ static Key each_word(Key a, F f) {
+    return ((unsigned long long)f((unsigned)(a >> 32)) << 32) | f((unsigned)a);
+  }
 };
 template <>
 struct KeyOps<double> {
@@ -53,10 +57,57 @@ struct KeyOps<double> {
   __device__ static double d2(const Key& a) { return a.d; }
   __device__ static int idx(const Key& a) { return a.i == INT_MAX ? -1 : a.i; }
   __device__ static Key shfl(const Key& a, int src) { return {__shfl(a.d, src, 64), __shfl(a.i, src, 64)}; }
-  __device__ static Key shfl_xor(const Key& a, int m) { return {__shfl_xor(a.d, m, 64), __shfl_xor(a.i, m, 64)}; }
   // field by field: a choice between two structs as lvalues would select
   // their addresses and keep the list in scratch memory
   __device__ static Key pick(bool c, const Key& a, const Key& b) { return {c ? a.d : b.d, c ? a.i : b.i}; }
+  template <class F>
+  __device__ static Key each_word(const Key& a, F f) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(a.d);
+    const unsigned long long w = ((unsigned long long)f((unsigned)(u >> 32)) << 32) | f((unsigned)u);
+    return {__longlong_as_double((long long)w), (int)f((unsigned)a.i)};
+  }
+};
+
+// Moves of 32-bit words between the lanes of a group of G consecutive lanes.
+// For G = 4 or 8 they are DPP row operations, which stay in the vector ALU
+// (controls: quad_perm [1,0,3,2] = 0xB1 takes lane ^ 1, [2,3,0,1] = 0x4E
+// lane ^ 2, [3,2,1,0] = 0x1B reverses a quad, [3,3,3,3] = 0xFF broadcasts
+// its last lane; row_shr:1 = 0x111 takes lane - 1 within a row of 16;
+// row_half_mirror = 0x141 takes lane 7 - i within each eight); other group
+// sizes use the LDS permute.  Every lane of the group is active.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_mov(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+template <int G>
+struct LaneMove {
+  static constexpr bool kDpp = G == 4 || G == 8;
+  // the word of lane l ^ m (m a power of two below G)
+  __device__ static unsigned xor_(unsigned v, int m) {
+    if constexpr (kDpp) {
+      if (m == 1) return dpp_mov<0xB1>(v);
+      if (m == 2) return dpp_mov<0x4E>(v);
+      if (m == 4) return dpp_mov<0x141>(dpp_mov<0x1B>(v));  // i -> 3 - i in the quad, then 7 - i
+    }
+    return (unsigned)__shfl_xor((int)v, m, 64);
+  }
+  // the word of lane l - 1 (what group lane 0 receives is not used)
+  __device__ static unsigned prev(unsigned v, int lane) {
+    if constexpr (kDpp) return dpp_mov<0x111>(v);
+    return (unsigned)__shfl((int)v, lane > 0 ? lane - 1 : 0, 64);
+  }
+  // the word of the group's last lane
+  __device__ static unsigned last(unsigned v, int gb, int l) {
+    if constexpr (G == 4) {
+      return dpp_mov<0xFF>(v);
+    } else if constexpr (G == 8) {
+      const unsigned a = dpp_mov<0xFF>(v);  // each quad: its last lane
+      const unsigned b = dpp_mov<0x141>(a);  // the other quad's
+      return l < 4 ? b : a;
+    } else {
+      return (unsigned)__shfl((int)v, gb + G - 1, 64);
+    }
+  }
 };
 
 // Ascending list of K keys over a group of G lanes: lane l holds ranks
@@ -70,7 +121,10 @@ struct GroupList {
 #pragma unroll
     for (int e = 0; e < E; ++e) key[e] = O::inf();
   }
-  __device__ Key worst(int gb) const { return O::shfl(key[E - 1], gb + G - 1); }
+  using LM = LaneMove<G>;
+  __device__ Key worst(int gb, int l) const {
+    return O::each_word(key[E - 1], [&](unsigned w) { return LM::last(w, gb, l); });
+  }
   // insert x (the same in every lane): its rank is the number of smaller
   // keys; ranks above it move up by one, the old k-th falls off
   __device__ void insert(const Key& x, int lane, int l) {
@@ -78,8 +132,8 @@ struct GroupList {
 #pragma unroll
     for (int e = 0; e < E; ++e) c += O::less(key[e], x) ? 1 : 0;
 #pragma unroll
-    for (int o = 1; o < G; o <<= 1) c += __shfl_xor(c, o, 64);
-    const Key prev = O::shfl(key[E - 1], lane > 0 ? lane - 1 : 0);
+    for (int o = 1; o < G; o <<= 1) c += (int)LM::xor_((unsigned)c, o);
+    const Key prev = O::each_word(key[E - 1], [&](unsigned w) { return LM::prev(w, lane); });
 #pragma unroll
     for (int e = E - 1; e >= 0; --e) {
       const int p = l * E + e;
@@ -112,7 +166,7 @@ struct GroupList {
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             const int i = l * E + e;
-            const Key o = O::shfl_xor(key[e], js / E);
+            const Key o = O::each_word(key[e], [&](unsigned w) { return LM::xor_(w, js / E); });
             const bool keep_min = (((i & ks) == 0) == ((i & js) == 0));
             const bool o_less = O::less(o, key[e]);
             key[e] = O::pick(keep_min == o_less, o, key[e]);
@@ -192,7 +246,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 #pragma unroll
       for (int e = 0; e < E; ++e) L.key[e] = gfill[l * E + e];
       L.sort(l);
-      wk = L.worst(gb);
+      wk = L.worst(gb, l);
       filling = false;
       pass = valid && pos >= K && O::less(ck, wk);  // the batch's candidates past the first K
     } else {
@@ -203,7 +257,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
       const int b = __ffsll((long long)m) - 1;
       const Key x = O::shfl(ck, gb + b);
       L.insert(x, lane, l);
-      wk = L.worst(gb);
+      wk = L.worst(gb, l);
       pass = pass && l != b && O::less(ck, wk);
       m = (__ballot(pass) >> gb) & gmask;
     }
@@ -346,7 +400,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 #pragma unroll
     for (int e = 0; e < E; ++e) L.key[e] = O::pick(l * E + e < nfill, gfill[l * E + e], O::inf());
     L.sort(l);
-    wk = L.worst(gb);
+    wk = L.worst(gb, l);
     filling = false;
   }
 
