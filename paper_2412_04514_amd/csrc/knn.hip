@@ -177,7 +177,7 @@ struct GroupList {
   }
 };
 
-// Held to 6 waves per SIMD (80 VGPRs, 100-140 bytes per lane of spills): the
+// Held to 6 waves per SIMD (80 VGPRs, 164 bytes per lane of scratch): the
 // search is latency-bound; at k = 64 on clustered input six waves measured 4%
 // faster than five (and 10% faster than four, without spills), seven and
 // eight slower again.
