@@ -195,9 +195,48 @@ __device__ __forceinline__ M bitm(int i) {
   return M(1) << i;
 }
 
+// Lane moves inside a row of 16 lanes by DPP, which stays in the vector ALU
+// (controls: quad_perm [1,0,3,2] = 0xB1 takes lane ^ 1, [2,3,0,1] = 0x4E
+// lane ^ 2, [3,2,1,0] = 0x1B reverses a quad; row_shr:n = 0x110 + n takes
+// lane - n; row_mirror = 0x140 takes lane 15 - i, row_half_mirror = 0x141
+// lane 7 - i within each eight).  Moves across rows use the LDS permute.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_mov(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+// the word of lane ^ m (m is a constant once the callers' loops unroll)
+__device__ __forceinline__ unsigned xor_word(unsigned v, int m) {
+  switch (m) {
+    case 1: return dpp_mov<0xB1>(v);
+    case 2: return dpp_mov<0x4E>(v);
+    case 4: return dpp_mov<0x141>(dpp_mov<0x1B>(v));  // i -> 3 - i in the quad, then 7 - i
+    case 8: return dpp_mov<0x140>(dpp_mov<0x141>(v));  // 7 - i in the eight, then 15 - i
+    default: return (unsigned)__shfl_xor((int)v, m, 64);
+  }
+}
+// the word of lane - n (n = 1, 2, 4, 8; lanes below n of the row receive 0)
+__device__ __forceinline__ unsigned up_word(unsigned v, int n) {
+  switch (n) {
+    case 1: return dpp_mov<0x111>(v);
+    case 2: return dpp_mov<0x112>(v);
+    case 4: return dpp_mov<0x114>(v);
+    default: return dpp_mov<0x118>(v);
+  }
+}
+// value of lane ^ m inside groups of w lanes; every lane of the group is
+// active
 template <typename T>
 __device__ __forceinline__ T shfl_xor_w(T v, int m, int w) {
-  return __shfl_xor(v, m, w);
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "one or two words");
+  if (m >= 16) return __shfl_xor(v, m, w);
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, xor_word(__builtin_bit_cast(unsigned, v), m));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long r =
+        ((unsigned long long)xor_word((unsigned)(u >> 32), m) << 32) | xor_word((unsigned)u, m);
+    return __builtin_bit_cast(T, r);
+  }
 }
 
 // FP64 plane of a cell (generator p): the bisector with point `id` (>= 0) or
@@ -328,7 +367,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TMAX <= 64 ?
     int x = v;
 #pragma unroll
     for (int o = 1; o < L; o <<= 1) {
-      const int y = __shfl_up(x, o, L);
+      const int y = L <= 16 ? (int)up_word((unsigned)x, o) : __shfl_up(x, o, L);
       if (j >= o) x += y;
     }
     tot = __shfl(x, L - 1, L);
