@@ -81,13 +81,14 @@ __device__ __forceinline__ unsigned dpp_mov(unsigned v) {
 }
 template <int G>
 struct LaneMove {
-  static constexpr bool kDpp = G == 4 || G == 8;
+  static constexpr bool kDpp = G == 4 || G == 8 || G == 16;
   // the word of lane l ^ m (m a power of two below G)
   __device__ static unsigned xor_(unsigned v, int m) {
     if constexpr (kDpp) {
       if (m == 1) return dpp_mov<0xB1>(v);
       if (m == 2) return dpp_mov<0x4E>(v);
       if (m == 4) return dpp_mov<0x141>(dpp_mov<0x1B>(v));  // i -> 3 - i in the quad, then 7 - i
+      if (m == 8) return dpp_mov<0x140>(dpp_mov<0x141>(v));  // 7 - i in the eight, then 15 - i
     }
     return (unsigned)__shfl_xor((int)v, m, 64);
   }
@@ -104,6 +105,9 @@ struct LaneMove {
       const unsigned a = dpp_mov<0xFF>(v);  // each quad: its last lane
       const unsigned b = dpp_mov<0x141>(a);  // the other quad's
       return l < 4 ? b : a;
+    } else if constexpr (G == 16) {
+      const unsigned a = dpp_mov<0xFF>(v), b = dpp_mov<0x140>(a), c = dpp_mov<0x141>(a), d = dpp_mov<0x140>(c);
+      return l < 4 ? b : (l < 8 ? d : (l < 12 ? c : a));
     } else {
       return (unsigned)__shfl((int)v, gb + G - 1, 64);
     }
@@ -542,7 +546,7 @@ votess_status dispatch_k(int k, const void* sorted, int n, const GridDev& G, con
     VT_KNN_CASE(24, 8)
     VT_KNN_CASE(32, 8)
     VT_KNN_CASE(48, 16)
-    VT_KNN_CASE(64, 8)
+    VT_KNN_CASE(64, 16)
     VT_KNN_CASE(128, 16)
     VT_KNN_CASE(256, 32)
     default:
