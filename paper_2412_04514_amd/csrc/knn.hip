@@ -69,12 +69,13 @@ struct KeyOps<double> {
 };
 
 // Moves of 32-bit words between the lanes of a group of G consecutive lanes.
-// For G = 4 or 8 they are DPP row operations, which stay in the vector ALU
-// (controls: quad_perm [1,0,3,2] = 0xB1 takes lane ^ 1, [2,3,0,1] = 0x4E
+// For G = 4, 8 or 16 they are DPP row operations, which stay in the vector
+// ALU (controls: quad_perm [1,0,3,2] = 0xB1 takes lane ^ 1, [2,3,0,1] = 0x4E
 // lane ^ 2, [3,2,1,0] = 0x1B reverses a quad, [3,3,3,3] = 0xFF broadcasts
 // its last lane; row_shr:1 = 0x111 takes lane - 1 within a row of 16;
-// row_half_mirror = 0x141 takes lane 7 - i within each eight); other group
-// sizes use the LDS permute.  Every lane of the group is active.
+// row_mirror = 0x140 takes lane 15 - i within the row, row_half_mirror =
+// 0x141 lane 7 - i within each eight); a group of 32 or 64 uses the LDS
+// permute.  Every lane of the group is active.
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp_mov(unsigned v) {
   return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
