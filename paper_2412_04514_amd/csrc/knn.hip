@@ -182,10 +182,10 @@ struct GroupList {
   }
 };
 
-// Held to 6 waves per SIMD (80 VGPRs, 164 bytes per lane of scratch): the
-// search is latency-bound; at k = 64 on clustered input six waves measured 4%
-// faster than five (and 10% faster than four, without spills), seven and
-// eight slower again.
+// Held to 6 waves per SIMD (80 VGPRs; the k = 64 float kernel keeps 132
+// bytes per lane in scratch): the search is latency-bound; at k = 64 on
+// clustered input six waves measured faster than five (3%), four (10%,
+// without spills), seven (5%) and eight (16%).
 // Blocks are taken in an XCD-aware order: the hardware deals launched
 // blocks round-robin over the eight XCDs, so launched block b runs logical
 // block (b mod 8) per + b / 8 (per = blocks / 8, rounded up; the launch is
