@@ -578,10 +578,12 @@ static votess_status run_grad(votess_kmodel* km, const float* feats, const uint8
   return VOTESS_OK;
 }
 
-// Learned first pass of votess_tessellate: 16-NN + features, network choice
-// of a bucket per cell, then per bucket a k-NN pass and a clip pass; with
-// `stream` the clip pass goes on by grid rings where the list does not
-// certify (else those cells are left for the retry ladder).
+// Learned first pass of votess_tessellate: one k-NN pass at the largest
+// bucket for every cell, the features from each row's first 16 entries, the
+// network's bucket per cell, then per bucket a clip pass over the first k
+// entries of its cells' rows; with `stream` the clip pass goes on by grid
+// rings where the list does not certify (else those cells are left for the
+// retry ladder).
 votess_status learned_first_pass(votess_ctx* ctx, votess_kmodel* km, double tau, const void* sorted, int n,
                                  const votess_grid& grid, const int32_t* cell_start, const ClipLaunch& base,
                                  int stream, int32_t* cells_buf, votess_stats& S, hipStream_t st) {
