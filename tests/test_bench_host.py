@@ -23,3 +23,10 @@ def test_clip_traffic_summary_is_found_and_complete():
         assert bench.clip_traffic(wl) == float(vals["bytes per step"])
     else:
         assert bench.clip_traffic(wl) is None
+
+
+def test_more_than_one_gpu_is_refused(capsys):
+    # the tessellation runs on one GPU; asking for more ends with a message
+    # before anything touches the device
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU only" in capsys.readouterr().err
