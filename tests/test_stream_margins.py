@@ -57,3 +57,25 @@ def test_vertices_reaching_the_list_ball_are_kept():
         two_c = 2 * float(np.sqrt(np.sum(np.asarray(v, np.float64) ** 2)))
         dk2 = f32((two_c * (1.0 - 1e-7)) ** 2)  # the ball of c = v reaches past it
         assert not rad_f32(v, e) < rlim_f32(dk2)
+
+
+def d2_f32(q, p):
+    # the clip's float d^2: each coordinate difference rounded to float, each
+    # square rounded, (x^2 + y^2) + z^2 with no fused multiply-add
+    dx, dy, dz = (f32(f32(a) - f32(b)) for a, b in zip(q, p))
+    return f32(f32(f32(dx * dx) + f32(dy * dy)) + f32(dz * dz))
+
+
+def test_float_d2_within_the_list_ball_margin():
+    # a box skipped as inside the list's ball, d^2 < d_k^2 (1 - 1e-6) in exact
+    # arithmetic, holds only points whose float d^2 is below the list's float
+    # d_k^2: the float d^2 is within 1e-6 relative of the exact one
+    rng = np.random.default_rng(9)
+    p = rng.uniform(0, 1, (50000, 3)).astype(f32)
+    q = (p.astype(np.float64) + rng.standard_normal((50000, 3)) * 10.0 ** rng.uniform(-5, -1, (50000, 1)))
+    q = np.clip(q, 0, 1).astype(f32)
+    exact = np.sum((q.astype(np.float64) - p.astype(np.float64)) ** 2, axis=1)
+    got = np.array([d2_f32(a, b) for a, b in zip(q, p)], dtype=np.float64)
+    keep = exact > 0
+    rel = np.abs(got[keep] - exact[keep]) / exact[keep]
+    assert rel.max() < 1e-6 / 2
